@@ -1,0 +1,126 @@
+/*
+ * ipscshuf: in-place parallel ScatterShuffle on one MI355X (gfx950).
+ *
+ * Generates a uniformly random permutation of a device array in place, as
+ * defined by M. Penschuck, "Engineering Shared-Memory Parallel Shuffling to
+ * Generate Random Permutations In-Place" (arXiv 2302.03317):
+ *   - ScatterShuffle (Sec. 2.2, Sec. 3.1): every element gets a uniform random
+ *     bucket, buckets become contiguous regions, every region is shuffled
+ *     recursively, and Fisher-Yates (Fig. 1) finishes small regions;
+ *   - one recursion level is RoughScatter (Sec. 3.2) with each tile owning a
+ *     piece of every bucket (Sec. 4.1), followed by the fix-up that
+ *     FineScatter performs (Sec. 3.3);
+ *   - the permutation is reproducible from the seed and independent of
+ *     scheduling (Sec. 4): every random draw is a Philox4x32-10 output keyed by
+ *     (seed, stream id, recursion level, position).
+ *
+ * The exact permutation is fixed by definition version 1 (see
+ * shuffle_definition_version) and the parameters shuf_params_t: two calls
+ * with the same (n, elem_bytes, seed, stream_id, params) apply the same
+ * permutation to any input contents.
+ *
+ * Conventions for every entry point:
+ *   - return 0 on success, a negative SHUF_E* code on failure;
+ *   - `ptr` is device memory owned by the caller (e.g. a torch tensor's
+ *     data_ptr()); the library never frees it;
+ *   - `stream` is a hipStream_t (NULL = the null stream).  The work runs on
+ *     that stream; the call returns after it has completed (the library
+ *     synchronises the stream to plan each recursion level);
+ *   - argument errors are detected before any GPU work starts, and then the
+ *     data is untouched; after SHUF_EHIP the contents are unspecified;
+ *   - calls may come from several host threads; calls on one device are
+ *     serialised by the library.
+ */
+#ifndef IPSCSHUF_H
+#define IPSCSHUF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHUF_OK 0
+#define SHUF_EINVAL -1       /* invalid argument */
+#define SHUF_ENOMEM -2       /* device or pinned host memory could not be obtained */
+#define SHUF_EHIP -3         /* a HIP call or kernel launch failed */
+#define SHUF_EUNSUPPORTED -4 /* valid, but beyond what this implementation handles */
+
+/* Parameters that are part of the permutation's definition.
+ *   tile       T: elements one tile holds; tile * elem_bytes <= 131072 and
+ *              tile >= 2^kmax_log2 + 1
+ *   kmax_log2  largest bucket-count exponent (k <= 2^kmax_log2), 1..8
+ *   n0         base-case size: subproblems of at most n0 elements are
+ *              finished by Fisher-Yates; >= 1
+ *   lmax       recursion cap: a subproblem at level lmax is finished by
+ *              Fisher-Yates; <= 255 */
+typedef struct {
+    uint32_t tile;
+    uint32_t kmax_log2;
+    uint32_t n0;
+    uint32_t lmax;
+} shuf_params_t;
+
+/* Version of the permutation definition implemented; changes whenever the
+ * output for given (inputs, n, elem_bytes, seed, stream_id, params) changes. */
+uint32_t shuffle_definition_version(void);
+
+/* Default parameters for n elements of elem_bytes each (4, 8 or 16):
+ * tile = 131072 / elem_bytes, kmax_log2 = 8, n0 = 64, lmax = 32.
+ * Returns SHUF_EINVAL for a null `out` or an unsupported width. */
+int shuf_default_params(uint64_t n, uint32_t elem_bytes, shuf_params_t* out);
+
+/* Shuffle n elements of elem_bytes (4, 8 or 16) bytes at device pointer ptr
+ * in place, with stream id 0 and the default parameters.
+ *   ptr         device pointer, aligned to elem_bytes; may be NULL if n <= 1
+ *   n           element count, n < 2^40
+ *   elem_bytes  4, 8 or 16; elements are moved as opaque words of that size
+ *   seed        64-bit seed
+ * Errors: SHUF_EINVAL (NULL ptr with n > 1, bad width, misaligned ptr),
+ * SHUF_EUNSUPPORTED (n too large), SHUF_ENOMEM, SHUF_EHIP. */
+int shuffle_inplace(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream);
+
+/* As shuffle_inplace with an explicit stream id (the fourth Philox counter
+ * word; distinct ids give independent permutations for one seed) and explicit
+ * parameters.  `params` must not be NULL.  Additional errors: SHUF_EINVAL for
+ * parameters outside the ranges above, SHUF_EUNSUPPORTED when the parameters
+ * need more LDS than one workgroup has. */
+int shuffle_inplace_ex(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                       uint32_t stream_id, const shuf_params_t* params, void* stream);
+
+/* Shuffle `count` independent arrays packed back to back at ptr, each in
+ * place.  Array j occupies elements [offsets[j], offsets[j+1]) and is shuffled
+ * exactly as shuffle_inplace_ex(ptr + offsets[j] * elem_bytes,
+ * offsets[j+1] - offsets[j], elem_bytes, seed, j, default params).  All arrays
+ * are processed together, level by level, in shared launches.
+ *   offsets     HOST array of count + 1 non-decreasing element offsets
+ *   count       number of arrays, < 2^32
+ * Errors: SHUF_EINVAL (NULL ptr or offsets, decreasing offsets, bad width or
+ * alignment), SHUF_EUNSUPPORTED, SHUF_ENOMEM, SHUF_EHIP. */
+int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
+                    uint64_t seed, void* stream);
+
+/* Human-readable text of an error code (static storage). */
+const char* shuffle_strerror(int code);
+
+/* Statistics of the most recent successful call on the calling thread's
+ * current device: levels run through the tiled pass, tiles launched, mover
+ * elements routed through the workspace, subproblems finished in LDS, and
+ * peak workspace bytes.  For tests and benchmarks; returns SHUF_EINVAL for a
+ * NULL pointer. */
+typedef struct {
+    uint32_t tiled_levels;
+    uint32_t reserved;
+    uint64_t tiles;
+    uint64_t movers;
+    uint64_t leaves;
+    uint64_t fy_fallback;
+    uint64_t workspace_bytes;
+} shuf_stats_t;
+int shuffle_last_stats(shuf_stats_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

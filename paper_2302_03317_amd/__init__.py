@@ -1,0 +1,185 @@
+"""In-place parallel ScatterShuffle on one MI355X (gfx950).
+
+A thin ctypes binding over ``libipscshuf.so`` (C ABI declared in
+``include/ipscshuf.h``).  Every step of the shuffle runs in the library's HIP
+kernels; this module only marshals arguments.  PyTorch is used for device
+memory and streams.  There is no CPU fallback: without the built library the
+calls raise.
+
+The permutation follows arXiv 2302.03317 (Penschuck): ScatterShuffle with
+RoughScatter and a FineScatter-style fix-up, recursing to Fisher-Yates.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libipscshuf.so")
+
+SHUF_OK = 0
+SHUF_EINVAL = -1
+SHUF_ENOMEM = -2
+SHUF_EHIP = -3
+SHUF_EUNSUPPORTED = -4
+
+
+class ShuffleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} (code {code})")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("tile", ctypes.c_uint32),
+        ("kmax_log2", ctypes.c_uint32),
+        ("n0", ctypes.c_uint32),
+        ("lmax", ctypes.c_uint32),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("tiled_levels", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("tiles", ctypes.c_uint64),
+        ("movers", ctypes.c_uint64),
+        ("leaves", ctypes.c_uint64),
+        ("fy_fallback", ctypes.c_uint64),
+        ("workspace_bytes", ctypes.c_uint64),
+    ]
+
+
+@dataclass(frozen=True)
+class Params:
+    """tile: elements per tile; kmax_log2: max bucket-count exponent;
+    n0: base-case size; lmax: recursion cap."""
+
+    tile: int
+    kmax_log2: int = 8
+    n0: int = 64
+    lmax: int = 32
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                "(there is no CPU fallback)"
+            )
+        L = ctypes.CDLL(LIB_PATH)
+        u32, u64, vp, i = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
+        L.shuffle_definition_version.argtypes = []
+        L.shuffle_definition_version.restype = u32
+        L.shuf_default_params.argtypes = [u64, u32, ctypes.POINTER(_Params)]
+        L.shuf_default_params.restype = i
+        L.shuffle_inplace.argtypes = [vp, u64, u32, u64, vp]
+        L.shuffle_inplace.restype = i
+        L.shuffle_inplace_ex.argtypes = [vp, u64, u32, u64, u32, ctypes.POINTER(_Params), vp]
+        L.shuffle_inplace_ex.restype = i
+        L.shuffle_batched.argtypes = [vp, ctypes.POINTER(u64), u64, u32, u64, vp]
+        L.shuffle_batched.restype = i
+        L.shuffle_strerror.argtypes = [i]
+        L.shuffle_strerror.restype = ctypes.c_char_p
+        L.shuffle_last_stats.argtypes = [ctypes.POINTER(_Stats)]
+        L.shuffle_last_stats.restype = i
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().shuffle_strerror(code).decode()
+
+
+def definition_version() -> int:
+    return int(lib().shuffle_definition_version())
+
+
+def default_params(n: int, elem_bytes: int) -> Params:
+    p = _Params()
+    rc = lib().shuf_default_params(n, elem_bytes, ctypes.byref(p))
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuf_default_params")
+    return Params(p.tile, p.kmax_log2, p.n0, p.lmax)
+
+
+def _stream_handle(tensor, stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream(tensor.device).cuda_stream)
+
+
+def _geometry(tensor):
+    if not tensor.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not tensor.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    n = tensor.shape[0] if tensor.dim() > 0 else 0
+    row = 1
+    for s in tensor.shape[1:]:
+        row *= s
+    return n, tensor.element_size() * row
+
+
+def shuffle_inplace(tensor, seed: int, stream=None) -> None:
+    """Shuffle the rows of a contiguous GPU tensor in place (row = one element
+    of 4, 8 or 16 bytes), stream id 0, default parameters."""
+    n, w = _geometry(tensor)
+    rc = lib().shuffle_inplace(
+        ctypes.c_void_p(tensor.data_ptr()), n, w, seed & (2**64 - 1), _stream_handle(tensor, stream)
+    )
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_inplace")
+
+
+def shuffle_inplace_ex(tensor, seed: int, stream_id: int = 0, params: Params | None = None,
+                       stream=None) -> None:
+    """Shuffle with an explicit stream id and parameters."""
+    n, w = _geometry(tensor)
+    p = params if params is not None else default_params(n, w)
+    cp = _Params(p.tile, p.kmax_log2, p.n0, p.lmax)
+    rc = lib().shuffle_inplace_ex(
+        ctypes.c_void_p(tensor.data_ptr()), n, w, seed & (2**64 - 1), stream_id, ctypes.byref(cp),
+        _stream_handle(tensor, stream),
+    )
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_inplace_ex")
+
+
+def shuffle_batched(tensor, offsets, seed: int, stream=None) -> None:
+    """Shuffle the arrays packed in `tensor` (rows [offsets[j], offsets[j+1])
+    form array j) in place, each with stream id j and default parameters."""
+    n, w = _geometry(tensor)
+    offs = [int(o) for o in offsets]
+    if len(offs) < 1 or offs[-1] > n:
+        raise ValueError("offsets must end within the tensor")
+    arr = (ctypes.c_uint64 * len(offs))(*offs)
+    rc = lib().shuffle_batched(
+        ctypes.c_void_p(tensor.data_ptr()), arr, len(offs) - 1, w, seed & (2**64 - 1),
+        _stream_handle(tensor, stream),
+    )
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_batched")
+
+
+def last_stats() -> dict:
+    s = _Stats()
+    rc = lib().shuffle_last_stats(ctypes.byref(s))
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_last_stats")
+    return {f: int(getattr(s, f)) for f, _ in _Stats._fields_ if f != "reserved"}
+
+
+def raw_call(name: str, *args) -> int:
+    """Call a C entry point with raw arguments (for argument-error tests)."""
+    return getattr(lib(), name)(*args)

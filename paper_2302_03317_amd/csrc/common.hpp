@@ -1,0 +1,208 @@
+// Shared descriptors and small device helpers for the in-place ScatterShuffle
+// kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ipss {
+
+constexpr int kThreads = 1024;             // threads of a tile / leaf workgroup
+constexpr int kWaves = kThreads / 64;      // wave64
+constexpr uint32_t kTileBytesMax = 131072; // most bytes of one tile's elements
+constexpr uint32_t kKmax = 256;            // labels live in one byte
+constexpr uint32_t kChunk = 256;           // tiles per chunk of the table scans
+constexpr uint32_t kLdsBytesMax = 163840;  // LDS of one CU on gfx950
+
+struct Params {
+    uint32_t tile;      // T: most elements a tile holds
+    uint32_t kmax_log2; // largest bucket-count exponent
+    uint32_t n0;        // base-case size
+    uint32_t lmax;      // recursion cap
+};
+
+// One subproblem of the tiled regime at the current level.
+struct SubDesc {
+    uint64_t elem_off;  // start of its array in the buffer, in elements
+    uint64_t base;      // start of the subproblem inside its array (positions)
+    uint64_t m;         // elements
+    uint64_t tiles;     // P
+    uint64_t tile_off;  // first global tile of the level's launch
+    uint64_t tab_off;   // first entry of its per-(tile, bucket) tables (row = tile)
+    uint64_t chunk_off; // first chunk of its table scans
+    uint64_t chtab_off; // first entry of its per-(chunk, bucket) tables (row = chunk)
+    uint32_t bk_off;    // first entry of its per-bucket tables
+    uint32_t kappa;     // k = 2^kappa
+    uint32_t level;
+    uint32_t stream_id;
+};
+
+// One subproblem finished in LDS (fits a tile) or by the sequential fallback.
+struct LeafDesc {
+    uint64_t elem_off;
+    uint64_t base;
+    uint64_t m;
+    uint32_t level;
+    uint32_t stream_id;
+};
+
+// Piece t of equal region b of a subproblem of m elements cut into 2^kappa
+// regions and P tiles: [lo, lo + cap), relative to the subproblem start.
+// Region b is [floor(b*m/k), floor((b+1)*m/k)); piece t starts at
+// floor(t*len/P).  The product t*len is split as t*(len/P) + t*(len%P)/P so
+// that it stays inside 64 bits (the host ensures P <= 2^32).
+__host__ __device__ __forceinline__ uint64_t piece_offset(uint64_t t, uint64_t len, uint64_t P)
+{
+    const uint64_t q = len / P, r = len % P;
+    return t * q + (t * r) / P;
+}
+
+struct Piece {
+    uint64_t lo;
+    uint64_t cap;
+};
+
+__host__ __device__ __forceinline__ Piece piece_of(uint64_t m, uint32_t kappa, uint64_t P,
+                                                   uint64_t t, uint32_t b)
+{
+    const uint64_t e0 = (static_cast<uint64_t>(b) * m) >> kappa;
+    const uint64_t e1 = (static_cast<uint64_t>(b + 1) * m) >> kappa;
+    const uint64_t len = e1 - e0;
+    const uint64_t lo = e0 + piece_offset(t, len, P);
+    const uint64_t hi = e0 + piece_offset(t + 1, len, P);
+    return {lo, hi - lo};
+}
+
+// LDS layout of the tile and leaf kernels (bytes).
+__host__ __device__ __forceinline__ uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
+
+struct RoughLayout {
+    uint32_t stage;    // T elements of staging (labels and per-wave counts overlay it)
+    uint32_t tables;   // offset of the per-piece tables
+    uint32_t total;
+};
+
+__host__ __device__ __forceinline__ RoughLayout rough_layout(uint32_t T, uint32_t w, uint32_t kmax)
+{
+    const uint32_t overlay = align16(T) + kWaves * kmax * 4u;
+    uint32_t stage = align16(T * w);
+    if (overlay > stage) stage = align16(overlay);
+    // lo: (kmax+1) u64; qoff, cap, fill, ovt, hot, nblk: (kmax+1) u32 each
+    const uint32_t tables = (kmax + 1) * 8u + 6u * (kmax + 1) * 4u;
+    return {stage, stage, stage + align16(tables)};
+}
+
+struct LeafLayout {
+    uint32_t idx;      // T u16: original leaf index of the item at each position
+    uint32_t lab;      // T bytes: label bytes of the current level
+    uint32_t hist;     // kWaves + 1 rows of (kmax + 1) u32 counters (last row: totals)
+    uint32_t segs;     // two segment lists of seg_cap packed (start | len << 16) u32
+    uint32_t tmpk;     // seg_cap + 1 u32: children per segment, then their offsets
+    uint32_t misc;     // 64 u32 of scalars
+    uint32_t seg_cap;  // entries of one segment list
+    uint32_t total;    // bytes, the final staging copy of the elements overlays all
+};
+
+__host__ __device__ __forceinline__ LeafLayout leaf_layout(uint32_t T, uint32_t w, uint32_t kmax,
+                                                           uint32_t n0)
+{
+    // A splitting segment of len items has k < 2*len/G children, G = max(1, n0/2);
+    // one level therefore lists fewer than 2*T/G segments.
+    uint32_t g = n0 / 2;
+    if (g < 1) g = 1;
+    const uint32_t seg_cap = 2u * T / g + 64u;
+    LeafLayout L;
+    L.idx = 0;
+    L.lab = align16(T * 2u);
+    L.hist = L.lab + align16(T);
+    L.segs = L.hist + align16((kWaves + 1) * (kmax + 1) * 4u);
+    L.tmpk = L.segs + align16(2u * seg_cap * 4u);
+    L.misc = L.tmpk + align16((seg_cap + 1) * 4u);
+    L.seg_cap = seg_cap;
+    const uint32_t work = L.misc + 64u * 4u;
+    const uint32_t stage = align16(T * w);
+    L.total = work > stage ? work : stage;
+    return L;
+}
+
+// ---- wave helpers (device) ----
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ uint32_t bits_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (static_cast<int>(lane_id()) >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_inclusive_sum64(uint64_t v)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t o = __shfl_up(v, d, 64);
+        if (static_cast<int>(lane_id()) >= d) v += o;
+    }
+    return v;
+}
+
+// Exclusive prefix sum of a[0..n) in place and a[n] = total; called by one
+// whole wave.
+__device__ __forceinline__ void wave_exclusive_scan(uint32_t* a, uint32_t n)
+{
+    const uint32_t lane = lane_id();
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < n; base += 256) {
+        uint32_t v[4];
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t j = base + lane * 4 + i;
+            v[i] = j < n ? a[j] : 0u;
+            s += v[i];
+        }
+        const uint32_t incl = wave_inclusive_sum(s);
+        uint32_t run = carry + incl - s;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t j = base + lane * 4 + i;
+            if (j < n) a[j] = run;
+            run += v[i];
+        }
+        carry += __shfl(incl, 63, 64);
+    }
+    if (lane == 0) a[n] = carry;
+}
+
+// Largest i in [0, n) with a[i] <= x, for a non-decreasing a with a[0] <= x.
+__device__ __forceinline__ uint32_t upper_index(const uint32_t* a, uint32_t n, uint32_t x)
+{
+    uint32_t lo = 0, hi = n;  // invariant: a[lo] <= x, answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t upper_index64(const uint64_t* a, uint32_t n, uint64_t x)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace ipss

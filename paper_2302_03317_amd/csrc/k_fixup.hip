@@ -1,0 +1,395 @@
+// Fix-up of a tiled level (the role of FineScatter, arXiv 2302.03317 Sec. 3.3).
+//
+// After the rough pass every tile has written its per-bucket counts.  From
+// them the final bucket sizes N_b and starts S_b follow, so the bucket
+// boundaries move from the equal split to the exact split.  An item is kept
+// where the rough pass put it when that slot lies inside its final region;
+// every other item is a mover.  Movers of bucket b are taken in (tile, read
+// order) order and fill the free slots of the final region F_b in ascending
+// order.  The tables below give every (tile, bucket) pair its share of that
+// order; the gather kernel copies movers to a workspace and the scatter
+// kernel copies them into the free slots.
+//
+// All table kernels work on the level's subproblems at once.  Per-(tile,
+// bucket) columns are summed in chunks of kChunk tiles, chunk sums are
+// scanned per bucket, and the in-chunk prefixes are materialised last.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ipss {
+
+namespace {
+
+constexpr int kTabThreads = 256;
+
+// Per (tile, bucket): the rough piece, how much of it was filled, the part of
+// the placed front that lies inside the final region (kept), the displaced
+// and the staged (overflow) counts.
+struct Stats {
+    uint64_t lo;       // piece start (relative to the subproblem)
+    uint64_t cap;
+    uint64_t fill;
+    uint64_t kept_lo;  // kept range [kept_lo, kept_lo + kept)
+    uint64_t kept;
+    uint64_t disp;     // placed but outside the final region
+    uint64_t ov;       // did not fit the piece
+};
+
+__device__ __forceinline__ Stats tile_bucket(const SubDesc& sd, uint64_t t, uint32_t b,
+                                             uint32_t cnt, uint64_t S, uint64_t N)
+{
+    Stats st;
+    const Piece pc = piece_of(sd.m, sd.kappa, sd.tiles, t, b);
+    st.lo = pc.lo;
+    st.cap = pc.cap;
+    st.fill = cnt < pc.cap ? cnt : pc.cap;
+    st.ov = cnt - st.fill;
+    const uint64_t a = pc.lo > S ? pc.lo : S;
+    const uint64_t e = (pc.lo + st.fill) < (S + N) ? (pc.lo + st.fill) : (S + N);
+    st.kept = e > a ? e - a : 0;
+    st.kept_lo = e > a ? a : pc.lo;
+    st.disp = st.fill - st.kept;
+    return st;
+}
+
+__device__ __forceinline__ uint64_t chunk_tiles(const SubDesc& sd, uint64_t c, uint64_t* t0)
+{
+    *t0 = c * kChunk;
+    const uint64_t t1 = (*t0 + kChunk) < sd.tiles ? (*t0 + kChunk) : sd.tiles;
+    return t1 - *t0;
+}
+
+__device__ __forceinline__ uint64_t num_chunks(const SubDesc& sd)
+{
+    return (sd.tiles + kChunk - 1) / kChunk;
+}
+
+// chA[chunk][b] = sum of the chunk's counts of bucket b
+__global__ __launch_bounds__(kTabThreads) void k_chunk_count_sum(LevelTables T)
+{
+    const uint64_t g = blockIdx.x;
+    const SubDesc sd = T.subs[T.chunk_sub[g]];
+    const uint32_t k = 1u << sd.kappa;
+    const uint64_t c = g - sd.chunk_off;
+    uint64_t t0;
+    const uint64_t nt = chunk_tiles(sd, c, &t0);
+    for (uint32_t b = threadIdx.x; b < k; b += kTabThreads) {
+        uint64_t s = 0;
+        for (uint64_t i = 0; i < nt; ++i) s += T.cnt[sd.tab_off + (t0 + i) * k + b];
+        T.chA[sd.chtab_off + c * k + b] = s;
+    }
+}
+
+// N[b] = sum over chunks
+__global__ __launch_bounds__(kTabThreads) void k_bucket_count_total(LevelTables T)
+{
+    const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * kTabThreads + threadIdx.x;
+    if (gb >= T.nbuckets) return;
+    const SubDesc sd = T.subs[T.bk_sub[gb]];
+    const uint32_t k = 1u << sd.kappa;
+    const uint32_t b = static_cast<uint32_t>(gb - sd.bk_off);
+    const uint64_t nc = num_chunks(sd);
+    uint64_t run = 0;
+    for (uint64_t c = 0; c < nc; ++c) run += T.chA[sd.chtab_off + c * k + b];
+    T.N[gb] = run;
+}
+
+// S[b] = exclusive prefix of N over the subproblem's buckets
+__global__ void k_bucket_starts(LevelTables T)
+{
+    const SubDesc sd = T.subs[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const uint32_t k = 1u << sd.kappa;
+    uint64_t run = 0;
+    for (uint32_t b = 0; b < k; ++b) {
+        T.S[sd.bk_off + b] = run;
+        run += T.N[sd.bk_off + b];
+    }
+}
+
+// chA[chunk][b] = movers, chB[chunk][b] = kept items of the chunk's tiles
+__global__ __launch_bounds__(kTabThreads) void k_chunk_route_sum(LevelTables T)
+{
+    const uint64_t g = blockIdx.x;
+    const SubDesc sd = T.subs[T.chunk_sub[g]];
+    const uint32_t k = 1u << sd.kappa;
+    const uint64_t c = g - sd.chunk_off;
+    uint64_t t0;
+    const uint64_t nt = chunk_tiles(sd, c, &t0);
+    for (uint32_t b = threadIdx.x; b < k; b += kTabThreads) {
+        const uint64_t S = T.S[sd.bk_off + b], N = T.N[sd.bk_off + b];
+        uint64_t mv = 0, kp = 0;
+        for (uint64_t i = 0; i < nt; ++i) {
+            const uint64_t t = t0 + i;
+            const Stats st = tile_bucket(sd, t, b, T.cnt[sd.tab_off + t * k + b], S, N);
+            mv += st.disp + st.ov;
+            kp += st.kept;
+        }
+        T.chA[sd.chtab_off + c * k + b] = mv;
+        T.chB[sd.chtab_off + c * k + b] = kp;
+    }
+}
+
+// chunk sums -> exclusive chunk prefixes; M[b], K[b] totals
+__global__ __launch_bounds__(kTabThreads) void k_bucket_route_scan(LevelTables T)
+{
+    const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * kTabThreads + threadIdx.x;
+    if (gb >= T.nbuckets) return;
+    const SubDesc sd = T.subs[T.bk_sub[gb]];
+    const uint32_t k = 1u << sd.kappa;
+    const uint32_t b = static_cast<uint32_t>(gb - sd.bk_off);
+    const uint64_t nc = num_chunks(sd);
+    uint64_t rm = 0, rk = 0;
+    for (uint64_t c = 0; c < nc; ++c) {
+        const uint64_t i = sd.chtab_off + c * k + b;
+        const uint64_t vm = T.chA[i], vk = T.chB[i];
+        T.chA[i] = rm;
+        T.chB[i] = rk;
+        rm += vm;
+        rk += vk;
+    }
+    T.M[gb] = rm;
+    T.K[gb] = rk;
+}
+
+// MB = exclusive prefix of M over all buckets of the level (one workgroup)
+__global__ __launch_bounds__(1024) void k_workspace_bases(LevelTables T)
+{
+    __shared__ uint64_t part[1024];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t n = T.nbuckets;
+    const uint64_t per = (n + 1023) / 1024;
+    const uint64_t b0 = tid * per;
+    const uint64_t b1 = (b0 + per) < n ? (b0 + per) : n;
+    uint64_t s = 0;
+    for (uint64_t i = b0; i < b1; ++i) s += T.M[i];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t run = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const uint64_t v = part[i];
+            part[i] = run;
+            run += v;
+        }
+        *T.total = run;
+    }
+    __syncthreads();
+    uint64_t run = part[tid];
+    for (uint64_t i = b0; i < b1; ++i) {
+        const uint64_t v = T.M[i];
+        T.MB[i] = run;
+        run += v;
+    }
+}
+
+// mpre/kpre[tile][b]: movers / kept items of bucket b in earlier tiles
+__global__ __launch_bounds__(kTabThreads) void k_chunk_route_prefix(LevelTables T)
+{
+    const uint64_t g = blockIdx.x;
+    const SubDesc sd = T.subs[T.chunk_sub[g]];
+    const uint32_t k = 1u << sd.kappa;
+    const uint64_t c = g - sd.chunk_off;
+    uint64_t t0;
+    const uint64_t nt = chunk_tiles(sd, c, &t0);
+    for (uint32_t b = threadIdx.x; b < k; b += kTabThreads) {
+        const uint64_t S = T.S[sd.bk_off + b], N = T.N[sd.bk_off + b];
+        uint64_t rm = T.chA[sd.chtab_off + c * k + b];
+        uint64_t rk = T.chB[sd.chtab_off + c * k + b];
+        for (uint64_t i = 0; i < nt; ++i) {
+            const uint64_t t = t0 + i;
+            const uint64_t e = sd.tab_off + t * k + b;
+            const Stats st = tile_bucket(sd, t, b, T.cnt[e], S, N);
+            T.mpre[e] = rm;
+            T.kpre[e] = rk;
+            rm += st.disp + st.ov;
+            rk += st.kept;
+        }
+    }
+}
+
+// ---- gather: movers of one tile into the workspace ----
+template <typename E>
+__global__ __launch_bounds__(kTabThreads) void k_gather(uint8_t* __restrict__ buf,
+                                                        E* __restrict__ ws, LevelTables T)
+{
+    __shared__ uint64_t lo[kKmax], kept_lo[kKmax], base_w[kKmax];
+    __shared__ uint32_t fill[kKmax], kept[kKmax], disp[kKmax];
+    __shared__ uint32_t ovt[kKmax + 1], hot[kKmax + 1], outt[kKmax + 1];
+    const uint32_t tid = threadIdx.x, wv = tid >> 6;
+    const uint64_t g = blockIdx.x;
+    const SubDesc sd = T.subs[T.tile_sub[g]];
+    const uint64_t t = g - sd.tile_off;
+    const uint32_t k = 1u << sd.kappa;
+    const E* X = reinterpret_cast<const E*>(buf) + sd.elem_off + sd.base;
+    for (uint32_t b = tid; b < k; b += kTabThreads) {
+        const uint64_t e = sd.tab_off + t * k + b;
+        const uint64_t gb = sd.bk_off + b;
+        const Stats st = tile_bucket(sd, t, b, T.cnt[e], T.S[gb], T.N[gb]);
+        lo[b] = st.lo;
+        kept_lo[b] = st.kept_lo;
+        fill[b] = static_cast<uint32_t>(st.fill);
+        kept[b] = static_cast<uint32_t>(st.kept);
+        disp[b] = static_cast<uint32_t>(st.disp);
+        ovt[b] = static_cast<uint32_t>(st.ov);
+        hot[b] = static_cast<uint32_t>(st.cap - st.fill);
+        outt[b] = static_cast<uint32_t>(st.disp + st.ov);
+        base_w[b] = T.MB[gb] + T.mpre[e];
+    }
+    __syncthreads();
+    if (wv == 0) wave_exclusive_scan(ovt, k);
+    if (wv == 1) wave_exclusive_scan(hot, k);
+    if (wv == 2) wave_exclusive_scan(outt, k);
+    __syncthreads();
+    const uint32_t nout = outt[k];
+    for (uint32_t i = tid; i < nout; i += kTabThreads) {
+        const uint32_t b = upper_index(outt, k, i);
+        const uint32_t j = i - outt[b];
+        uint64_t pos;
+        if (j < disp[b]) {
+            // displaced: placed ranks outside the final region, in rank order
+            const uint64_t before = kept[b] ? kept_lo[b] - lo[b] : fill[b];
+            const uint64_t r = j < before ? j : (kept_lo[b] - lo[b]) + kept[b] + (j - before);
+            pos = lo[b] + r;
+        } else {
+            // staged: overflow o of bucket b sits in free slot ovt[b] + o of the tile
+            const uint32_t s = ovt[b] + (j - disp[b]);
+            const uint32_t bb = upper_index(hot, k, s);
+            pos = lo[bb] + fill[bb] + (s - hot[bb]);
+        }
+        const uint64_t widx = base_w[b] + j;
+        if (widx >= T.ws_cap || pos >= sd.m) {
+            atomicOr(T.err, 1u);
+            continue;
+        }
+        ws[widx] = X[pos];
+    }
+}
+
+// ---- scatter: free slots of the tile's pieces from the workspace ----
+template <typename E>
+__global__ __launch_bounds__(kTabThreads) void k_scatter(uint8_t* __restrict__ buf,
+                                                         const E* __restrict__ ws, LevelTables T)
+{
+    __shared__ uint64_t S[kKmax], Ktot[kKmax], MB[kKmax], lo[kKmax], kept_lo[kKmax], kpre[kKmax];
+    __shared__ uint32_t kept[kKmax], nkt[kKmax + 1];
+    const uint32_t tid = threadIdx.x, wv = tid >> 6;
+    const uint64_t g = blockIdx.x;
+    const SubDesc sd = T.subs[T.tile_sub[g]];
+    const uint64_t t = g - sd.tile_off;
+    const uint32_t k = 1u << sd.kappa;
+    E* X = reinterpret_cast<E*>(buf) + sd.elem_off + sd.base;
+    for (uint32_t b = tid; b < k; b += kTabThreads) {
+        const uint64_t e = sd.tab_off + t * k + b;
+        const uint64_t gb = sd.bk_off + b;
+        const Stats st = tile_bucket(sd, t, b, T.cnt[e], T.S[gb], T.N[gb]);
+        S[b] = T.S[gb];
+        Ktot[b] = T.K[gb];
+        MB[b] = T.MB[gb];
+        lo[b] = st.lo;
+        kept_lo[b] = st.kept_lo;
+        kept[b] = static_cast<uint32_t>(st.kept);
+        kpre[b] = T.kpre[e];
+        nkt[b] = static_cast<uint32_t>(st.cap - st.kept);
+    }
+    __syncthreads();
+    if (wv == 0) wave_exclusive_scan(nkt, k);
+    __syncthreads();
+    const uint32_t nfree = nkt[k];
+    for (uint32_t i = tid; i < nfree; i += kTabThreads) {
+        const uint32_t b = upper_index(nkt, k, i);  // piece of the free slot
+        const uint64_t j = i - nkt[b];
+        uint64_t x;
+        if (kept[b] == 0) {
+            x = lo[b] + j;
+        } else {
+            const uint64_t before = kept_lo[b] - lo[b];
+            x = j < before ? lo[b] + j : kept_lo[b] + kept[b] + (j - before);
+        }
+        const uint32_t fb = upper_index64(S, k, x);  // final bucket holding slot x
+        uint64_t kb;  // kept items of bucket fb below x
+        if (fb == b) {
+            kb = kpre[b] + ((kept[b] && x >= kept_lo[b] + kept[b]) ? kept[b] : 0);
+        } else {
+            // kept items of fb lie in its equal region, wholly below or above x
+            kb = fb < b ? Ktot[fb] : 0;
+        }
+        const uint64_t widx = MB[fb] + (x - S[fb]) - kb;
+        if (widx >= T.ws_cap || x >= sd.m) {
+            atomicOr(T.err, 2u);
+            continue;
+        }
+        X[x] = ws[widx];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_tables_sizes(const LevelTables& t, hipStream_t stream)
+{
+    if (t.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_count_sum, dim3(static_cast<uint32_t>(t.nchunks)), dim3(kTabThreads),
+                       0, stream, t);
+    hipLaunchKernelGGL(k_bucket_count_total,
+                       dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads - 1) / kTabThreads)),
+                       dim3(kTabThreads), 0, stream, t);
+    hipLaunchKernelGGL(k_bucket_starts, dim3(static_cast<uint32_t>(t.nsubs)), dim3(64), 0, stream, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables_routes(const LevelTables& t, hipStream_t stream)
+{
+    if (t.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_route_sum, dim3(static_cast<uint32_t>(t.nchunks)), dim3(kTabThreads),
+                       0, stream, t);
+    hipLaunchKernelGGL(k_bucket_route_scan,
+                       dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads - 1) / kTabThreads)),
+                       dim3(kTabThreads), 0, stream, t);
+    hipLaunchKernelGGL(k_workspace_bases, dim3(1), dim3(1024), 0, stream, t);
+    hipLaunchKernelGGL(k_chunk_route_prefix, dim3(static_cast<uint32_t>(t.nchunks)),
+                       dim3(kTabThreads), 0, stream, t);
+    return hipGetLastError();
+}
+
+template <typename E>
+static hipError_t gather_t(uint8_t* buf, uint8_t* ws, const LevelTables& t, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_gather<E>, dim3(static_cast<uint32_t>(t.ntiles)), dim3(kTabThreads), 0,
+                       stream, buf, reinterpret_cast<E*>(ws), t);
+    return hipGetLastError();
+}
+
+template <typename E>
+static hipError_t scatter_t(uint8_t* buf, const uint8_t* ws, const LevelTables& t,
+                            hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_scatter<E>, dim3(static_cast<uint32_t>(t.ntiles)), dim3(kTabThreads), 0,
+                       stream, buf, reinterpret_cast<const E*>(ws), t);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(uint32_t w, uint8_t* buf, uint8_t* ws, const LevelTables& t,
+                         hipStream_t stream)
+{
+    if (t.ntiles == 0) return hipSuccess;
+    switch (w) {
+    case 4: return gather_t<uint32_t>(buf, ws, t, stream);
+    case 8: return gather_t<uint64_t>(buf, ws, t, stream);
+    case 16: return gather_t<Elem16>(buf, ws, t, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_scatter(uint32_t w, uint8_t* buf, const uint8_t* ws, const LevelTables& t,
+                          hipStream_t stream)
+{
+    if (t.ntiles == 0) return hipSuccess;
+    switch (w) {
+    case 4: return scatter_t<uint32_t>(buf, ws, t, stream);
+    case 8: return scatter_t<uint64_t>(buf, ws, t, stream);
+    case 16: return scatter_t<Elem16>(buf, ws, t, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ipss

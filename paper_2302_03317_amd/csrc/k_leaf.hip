@@ -1,0 +1,368 @@
+// Subproblems that fit one tile, finished in LDS: the remaining recursion
+// levels of ScatterShuffle (arXiv 2302.03317, Sec. 3.1 / Fig. 2) and the
+// Fisher-Yates base case (Fig. 1).
+//
+// One workgroup per subproblem ("leaf").  The elements are loaded once into
+// registers at the start (the loads overlap all index work) and written once
+// at the end.  In between only 16-bit indices move: idx[x] is the original
+// leaf index of the item at position x.  Each in-tile level is a stable
+// counting sort of every splitting segment by its label; segments larger
+// than one wave can hold are split by the whole workgroup, the others by one
+// wave each.  Segments at the base case run Fisher-Yates, one lane per
+// segment.  Finally every item's destination is read off the index array and
+// the elements go through an LDS staging copy to HBM.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "rng.hpp"
+
+namespace ipss {
+
+namespace {
+
+constexpr uint32_t kRounds = 32;                  // index rounds held in registers
+constexpr uint32_t kWaveSegMax = 64u * kRounds;   // largest segment split by one wave
+
+__device__ __forceinline__ uint32_t seg_start(uint32_t e) { return e & 0xFFFFu; }
+__device__ __forceinline__ uint32_t seg_len(uint32_t e) { return e >> 16; }
+__device__ __forceinline__ uint32_t seg_pack(uint32_t s, uint32_t l) { return s | (l << 16); }
+
+// Bucket-count exponent of an in-tile segment: target size max(1, n0/2).
+__device__ __forceinline__ uint32_t kappa_in_tile(uint32_t m, const Params& prm)
+{
+    uint32_t g = prm.n0 / 2;
+    if (g < 1) g = 1;
+    uint32_t r = 1;
+    uint64_t reach = 2ull * g;
+    while (reach < m) {
+        reach <<= 1;
+        ++r;
+    }
+    const uint32_t h = (r + prm.kmax_log2 - 1) / prm.kmax_log2;
+    const uint32_t kap = (r + h - 1) / h;
+    return kap < prm.kmax_log2 ? kap : prm.kmax_log2;
+}
+
+// Fisher-Yates on idx[s0, s0 + len): i from len-1 down to 1, partner drawn
+// from [0, i] at position pbase + s0 + i.  One Philox block serves four
+// consecutive positions.
+__device__ void fy_segment(uint16_t* idx, uint32_t s0, uint32_t len, uint64_t pbase,
+                           uint32_t level, const Key& key)
+{
+    uint64_t cached = ~0ull;
+    Word4 v = {0, 0, 0, 0};
+    for (uint32_t i = len - 1; i >= 1; --i) {
+        const uint64_t p = pbase + s0 + i;
+        if ((p >> 2) != cached) {
+            cached = p >> 2;
+            v = fy_block(key, level, cached, 0);
+        }
+        const uint32_t j = fy_draw_from(key, level, p, i + 1, v);
+        const uint16_t a = idx[s0 + i];
+        idx[s0 + i] = idx[s0 + j];
+        idx[s0 + j] = a;
+    }
+}
+
+// Match the labels of one round: lanes with the same valid label.
+__device__ __forceinline__ uint64_t match_label(uint32_t l, bool valid, uint32_t kappa)
+{
+    uint64_t peers = __ballot(valid);
+    for (uint32_t i = 0; i < kappa; ++i) {
+        const bool bit = (l >> i) & 1u;
+        const uint64_t mb = __ballot(bit);
+        peers &= bit ? mb : ~mb;
+    }
+    return peers;
+}
+
+template <typename E, int EMAX>
+__global__ __launch_bounds__(kThreads) void k_leaf(uint8_t* __restrict__ buf,
+                                                   const LeafDesc* __restrict__ leaves,
+                                                   uint64_t seed, Params prm)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const LeafDesc ld = leaves[blockIdx.x];
+    const uint32_t m = static_cast<uint32_t>(ld.m);
+    const uint32_t kmax = 1u << prm.kmax_log2;
+    const uint32_t hs = kmax + 1;  // row stride of the counters
+    const LeafLayout LL = leaf_layout(prm.tile, sizeof(E), kmax, prm.n0);
+    uint16_t* idx = reinterpret_cast<uint16_t*>(smem + LL.idx);
+    uint8_t* lab = smem + LL.lab;
+    uint32_t* H = reinterpret_cast<uint32_t*>(smem + LL.hist);
+    uint32_t* Htot = H + kWaves * hs;
+    uint32_t* cur = reinterpret_cast<uint32_t*>(smem + LL.segs);
+    uint32_t* nxt = cur + LL.seg_cap;
+    uint32_t* tmpk = reinterpret_cast<uint32_t*>(smem + LL.tmpk);
+    uint32_t* misc = reinterpret_cast<uint32_t*>(smem + LL.misc);  // [0] segments, [1] big, [2..) big list
+    E* stage = reinterpret_cast<E*>(smem);
+
+    E* X = reinterpret_cast<E*>(buf) + ld.elem_off + ld.base;
+    const uint64_t pbase = ld.base;
+    const Key key = make_key(seed, ld.stream_id);
+
+    E data[EMAX];
+#pragma unroll
+    for (int r = 0; r < EMAX; ++r) {
+        const uint32_t q = r * kThreads + tid;
+        if (q < m) data[r] = X[q];
+    }
+    for (uint32_t x = tid; x < m; x += kThreads) idx[x] = static_cast<uint16_t>(x);
+    if (tid == 0) {
+        cur[0] = seg_pack(0, m);
+        misc[0] = 1;
+    }
+    __syncthreads();
+
+    uint32_t level = ld.level;
+    for (;;) {
+        const uint32_t nseg = misc[0];
+        if (nseg == 0) break;
+        __syncthreads();
+        if (tid == 0) misc[1] = 0;
+        __syncthreads();
+
+        // Classify the segments; base-case segments run Fisher-Yates now.
+        for (uint32_t i = tid; i < nseg; i += kThreads) {
+            const uint32_t e = cur[i];
+            const uint32_t s0 = seg_start(e), len = seg_len(e);
+            uint32_t kk = 0;
+            if (len >= 2) {
+                if (len <= prm.n0 || level >= prm.lmax) {
+                    fy_segment(idx, s0, len, pbase, level, key);
+                } else {
+                    kk = 1u << kappa_in_tile(len, prm);
+                    if (len > kWaveSegMax) misc[2 + atomicAdd(&misc[1], 1u)] = i;
+                }
+            }
+            tmpk[i] = kk;
+        }
+        // Label bytes of this level for every position of the leaf.
+        {
+            const uint64_t b0 = pbase >> 4;
+            const uint64_t nb = ((pbase + m - 1) >> 4) - b0 + 1;
+            for (uint64_t i = tid; i < nb; i += kThreads) {
+                const uint64_t B = b0 + i;
+                const Word4 v = label_block(key, level, B);
+#pragma unroll
+                for (uint32_t j = 0; j < 16; ++j) {
+                    const uint64_t p = B * 16 + j;
+                    if (p >= pbase && p < pbase + m)
+                        lab[p - pbase] = static_cast<uint8_t>(block_byte(v, j));
+                }
+            }
+        }
+        __syncthreads();
+        if (wv == 0) wave_exclusive_scan(tmpk, nseg);  // child offsets; tmpk[nseg] = total
+        __syncthreads();
+        const uint32_t nbig = misc[1];
+
+        // Large segments: the whole workgroup, one segment at a time.
+        for (uint32_t bi = 0; bi < nbig; ++bi) {
+            const uint32_t i = misc[2 + bi];
+            const uint32_t e = cur[i];
+            const uint32_t s0 = seg_start(e), len = seg_len(e), end = s0 + len;
+            const uint32_t kap = kappa_in_tile(len, prm), k = 1u << kap, sh = 8 - kap;
+            const uint32_t per_wave = ((len + kWaves * 64 - 1) / (kWaves * 64)) * 64;
+            const uint32_t rounds = per_wave / 64;
+            const uint32_t first = s0 + wv * per_wave + lane;
+            for (uint32_t j = tid; j < (kWaves + 1) * hs; j += kThreads) H[j] = 0;
+            __syncthreads();
+            uint32_t pk[kRounds];
+#pragma unroll
+            for (uint32_t r = 0; r < kRounds; ++r) {
+                if (r < rounds) {
+                    const uint32_t x = first + 64u * r;
+                    const bool valid = x < end;
+                    const uint32_t l = valid ? (lab[x] >> sh) : 0u;
+                    const uint64_t peers = match_label(l, valid, kap);
+                    const uint32_t below = bits_below(peers);
+                    uint32_t old = 0;
+                    if (valid) old = H[wv * hs + l];
+                    if (valid && below == 0) H[wv * hs + l] = old + static_cast<uint32_t>(__popcll(peers));
+                    pk[r] = valid ? (static_cast<uint32_t>(idx[x]) | ((old + below) << 16)) : 0u;
+                }
+            }
+            __syncthreads();
+            for (uint32_t l = tid; l < k; l += kThreads) {
+                uint32_t run = 0;
+                for (int w = 0; w < kWaves; ++w) {
+                    const uint32_t v = H[w * hs + l];
+                    H[w * hs + l] = run;
+                    run += v;
+                }
+                Htot[l] = run;
+            }
+            __syncthreads();
+            if (wv == 0) wave_exclusive_scan(Htot, k);
+            __syncthreads();
+            for (uint32_t l = tid; l < k; l += kThreads)
+                nxt[tmpk[i] + l] = seg_pack(s0 + Htot[l], Htot[l + 1] - Htot[l]);
+#pragma unroll
+            for (uint32_t r = 0; r < kRounds; ++r) {
+                if (r < rounds) {
+                    const uint32_t x = first + 64u * r;
+                    if (x < end) {
+                        const uint32_t l = lab[x] >> sh;
+                        idx[s0 + Htot[l] + H[wv * hs + l] + (pk[r] >> 16)] =
+                            static_cast<uint16_t>(pk[r] & 0xFFFFu);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        // Other splitting segments: one wave each.
+        for (uint32_t i = wv; i < nseg; i += kWaves) {
+            const uint32_t e = cur[i];
+            const uint32_t s0 = seg_start(e), len = seg_len(e), end = s0 + len;
+            if (len < 2 || len <= prm.n0 || level >= prm.lmax || len > kWaveSegMax) continue;
+            const uint32_t kap = kappa_in_tile(len, prm), k = 1u << kap, sh = 8 - kap;
+            uint32_t* Hw = H + wv * hs;
+            for (uint32_t j = lane; j <= k; j += 64) Hw[j] = 0;
+            const uint32_t rounds = (len + 63) / 64;
+            uint32_t pk[kRounds];
+#pragma unroll
+            for (uint32_t r = 0; r < kRounds; ++r) {
+                if (r < rounds) {
+                    const uint32_t x = s0 + 64u * r + lane;
+                    const bool valid = x < end;
+                    const uint32_t l = valid ? (lab[x] >> sh) : 0u;
+                    const uint64_t peers = match_label(l, valid, kap);
+                    const uint32_t below = bits_below(peers);
+                    uint32_t old = 0;
+                    if (valid) old = Hw[l];
+                    if (valid && below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
+                    pk[r] = valid ? (static_cast<uint32_t>(idx[x]) | ((old + below) << 16)) : 0u;
+                }
+            }
+            wave_exclusive_scan(Hw, k);
+            for (uint32_t l = lane; l < k; l += 64)
+                nxt[tmpk[i] + l] = seg_pack(s0 + Hw[l], Hw[l + 1] - Hw[l]);
+#pragma unroll
+            for (uint32_t r = 0; r < kRounds; ++r) {
+                if (r < rounds) {
+                    const uint32_t x = s0 + 64u * r + lane;
+                    if (x < end) {
+                        const uint32_t l = lab[x] >> sh;
+                        idx[s0 + Hw[l] + (pk[r] >> 16)] = static_cast<uint16_t>(pk[r] & 0xFFFFu);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) misc[0] = tmpk[nseg];
+        uint32_t* sw = cur;
+        cur = nxt;
+        nxt = sw;
+        ++level;
+        __syncthreads();
+    }
+
+    // idx[x] = original index of the item ending at x; invert it in place.
+    uint32_t v[kRounds];
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+        const uint32_t x = r * kThreads + tid;
+        if (x < m) v[r] = idx[x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+        const uint32_t x = r * kThreads + tid;
+        if (x < m) idx[v[r]] = static_cast<uint16_t>(x);
+    }
+    __syncthreads();
+    uint32_t dst[EMAX];
+#pragma unroll
+    for (int r = 0; r < EMAX; ++r) {
+        const uint32_t q = r * kThreads + tid;
+        if (q < m) dst[r] = idx[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < EMAX; ++r) {
+        const uint32_t q = r * kThreads + tid;
+        if (q < m) stage[dst[r]] = data[r];
+    }
+    __syncthreads();
+    for (uint32_t x = tid; x < m; x += kThreads) X[x] = stage[x];
+}
+
+template <typename E>
+__global__ void k_fy_global(uint8_t* __restrict__ buf, const LeafDesc* __restrict__ items,
+                            uint64_t seed)
+{
+    if (threadIdx.x != 0) return;
+    const LeafDesc ld = items[blockIdx.x];
+    E* X = reinterpret_cast<E*>(buf) + ld.elem_off + ld.base;
+    const Key key = make_key(seed, ld.stream_id);
+    for (uint64_t i = ld.m - 1; i >= 1; --i) {
+        const uint64_t p = ld.base + i;
+        const Word4 v = fy_block(key, ld.level, p >> 2, 0);
+        const uint64_t j = fy_draw_from(key, ld.level, p, static_cast<uint32_t>(i + 1), v);
+        const E a = X[i];
+        X[i] = X[j];
+        X[j] = a;
+    }
+}
+
+template <typename E>
+hipError_t leaf_t(uint8_t* buf, const LeafDesc* leaves, uint64_t n, uint64_t seed, const Params& prm,
+                  hipStream_t stream)
+{
+    constexpr int EMAX = static_cast<int>(kTileBytesMax / (sizeof(E) * kThreads));
+    const LeafLayout LL = leaf_layout(prm.tile, sizeof(E), 1u << prm.kmax_log2, prm.n0);
+    hipLaunchKernelGGL((k_leaf<E, EMAX>), dim3(static_cast<uint32_t>(n)), dim3(kThreads), LL.total,
+                       stream, buf, leaves, seed, prm);
+    return hipGetLastError();
+}
+
+template <typename E>
+hipError_t fy_t(uint8_t* buf, const LeafDesc* items, uint64_t n, uint64_t seed, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_fy_global<E>, dim3(static_cast<uint32_t>(n)), dim3(64), 0, stream, buf,
+                       items, seed);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_leaf(uint32_t w, uint8_t* buf, const LeafDesc* leaves, uint64_t nleaves,
+                       uint64_t seed, const Params& prm, hipStream_t stream)
+{
+    if (nleaves == 0) return hipSuccess;
+    switch (w) {
+    case 4: return leaf_t<uint32_t>(buf, leaves, nleaves, seed, prm, stream);
+    case 8: return leaf_t<uint64_t>(buf, leaves, nleaves, seed, prm, stream);
+    case 16: return leaf_t<Elem16>(buf, leaves, nleaves, seed, prm, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t set_leaf_lds_limits()
+{
+    hipError_t e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<uint32_t, 32>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<uint64_t, 16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<Elem16, 8>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+}
+
+hipError_t launch_fy_global(uint32_t w, uint8_t* buf, const LeafDesc* items, uint64_t count,
+                            uint64_t seed, hipStream_t stream)
+{
+    if (count == 0) return hipSuccess;
+    switch (w) {
+    case 4: return fy_t<uint32_t>(buf, items, count, seed, stream);
+    case 8: return fy_t<uint64_t>(buf, items, count, seed, stream);
+    case 16: return fy_t<Elem16>(buf, items, count, seed, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ipss

@@ -1,0 +1,61 @@
+// Launch wrappers of the shuffle kernels (one translation unit each).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace ipss {
+
+struct __attribute__((aligned(16))) Elem16 {
+    uint64_t lo, hi;
+};
+
+// Rough pass of one tiled level: one workgroup per tile.
+hipError_t launch_rough(uint32_t w, uint8_t* buf, const SubDesc* subs, const uint32_t* tile_sub,
+                        uint32_t* cnt_tab, uint64_t ntiles, uint64_t seed, const Params& prm,
+                        hipStream_t stream);
+hipError_t set_rough_lds_limits();
+
+// Device tables of one tiled level (see k_fixup.hip).
+struct LevelTables {
+    const SubDesc* subs;
+    const uint32_t* tile_sub;   // global tile -> subproblem
+    const uint32_t* chunk_sub;  // global chunk -> subproblem
+    const uint32_t* bk_sub;     // global bucket -> subproblem
+    uint32_t* cnt;              // [tile][bucket] counts from the rough pass
+    uint64_t* mpre;             // [tile][bucket] movers of earlier tiles (exclusive)
+    uint64_t* kpre;             // [tile][bucket] kept items of earlier tiles (exclusive)
+    uint64_t* chA;              // [chunk][bucket] scratch sums / prefixes
+    uint64_t* chB;
+    uint64_t* N;                // [bucket] final sizes
+    uint64_t* S;                // [bucket] final starts, relative to the subproblem
+    uint64_t* M;                // [bucket] movers
+    uint64_t* K;                // [bucket] kept items
+    uint64_t* MB;               // [bucket] workspace start of the bucket's movers
+    uint64_t* total;            // [1] workspace elements of the level
+    uint32_t* err;              // [1] set non-zero by a kernel that finds an index out of range
+    uint64_t ws_cap;            // workspace elements available to gather / scatter
+    uint64_t nsubs, ntiles, nchunks, nbuckets;
+};
+
+// Counts -> final sizes and starts; movers, kept prefixes; workspace bases.
+hipError_t launch_tables_sizes(const LevelTables& t, hipStream_t stream);
+hipError_t launch_tables_routes(const LevelTables& t, hipStream_t stream);
+// Fix-up: gather movers into the workspace, then scatter into free slots.
+hipError_t launch_gather(uint32_t w, uint8_t* buf, uint8_t* ws, const LevelTables& t,
+                         hipStream_t stream);
+hipError_t launch_scatter(uint32_t w, uint8_t* buf, const uint8_t* ws, const LevelTables& t,
+                          hipStream_t stream);
+
+// Subproblems that fit a tile: in-LDS levels and Fisher-Yates.
+hipError_t launch_leaf(uint32_t w, uint8_t* buf, const LeafDesc* leaves, uint64_t nleaves,
+                       uint64_t seed, const Params& prm, hipStream_t stream);
+hipError_t set_leaf_lds_limits();
+// Sequential Fisher-Yates in global memory (recursion cap reached on a
+// subproblem that does not fit a tile).
+hipError_t launch_fy_global(uint32_t w, uint8_t* buf, const LeafDesc* items, uint64_t count,
+                            uint64_t seed, hipStream_t stream);
+
+}  // namespace ipss

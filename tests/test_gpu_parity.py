@@ -1,0 +1,209 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle,
+element by element, on the same seeded inputs.  Integer work: bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lib():
+    import paper_2302_03317_amd as shuf
+
+    shuf.lib()
+    return shuf
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def to_dev(host: np.ndarray):
+    view = host.view(np.int32) if host.dtype == np.uint32 else host.view(np.int64)
+    return torch.from_numpy(view.copy()).to(_dev())
+
+
+def from_dev(t, like: np.ndarray) -> np.ndarray:
+    return t.cpu().numpy().view(like.dtype).reshape(like.shape)
+
+
+def gpu_shuffle(host, seed, params=None, stream_id=0):
+    shuf = _lib()
+    n = host.shape[0]
+    w = host.itemsize * (host.shape[1] if host.ndim > 1 else 1)
+    print(f"[gpu] n={n} w={w} seed={seed} stream={stream_id} params={params}", flush=True)
+    t = to_dev(host)
+    p = None if params is None else shuf.Params(params.tile, params.kmax_log2, params.n0, params.lmax)
+    shuf.shuffle_inplace_ex(t, seed, stream_id, p)
+    torch.cuda.synchronize()
+    return from_dev(t, host)
+
+
+def oracle_shuffle(host, seed, params, stream_id=0):
+    out = host.copy()
+    oracle.shuffle(out, seed, params, stream_id=stream_id)
+    return out
+
+
+def assert_same(got, want, what):
+    if not np.array_equal(got, want):
+        bad = np.nonzero((got != want).reshape(got.shape[0], -1).any(axis=1))[0]
+        raise AssertionError(f"{what}: {bad.size} rows differ, first at {bad[:8].tolist()}")
+
+
+TINY = [
+    oracle.Params(3, 1, 1, 4),
+    oracle.Params(4, 1, 2, 5),
+    oracle.Params(5, 2, 1, 3),
+    oracle.Params(9, 3, 1, 2),
+    oracle.Params(40, 3, 4, 32),
+    oracle.Params(64, 4, 8, 6),
+    oracle.Params(300, 5, 16, 32),
+    oracle.Params(1000, 8, 64, 32),
+    oracle.Params(4096, 8, 1, 3),
+]
+
+
+@pytest.mark.parametrize("p", TINY)
+def test_tiny_parameters_sweep(p):
+    """Tiny tiles force many tiles, movers, displaced items, in-LDS levels,
+    the recursion cap and the sequential fallback at small n."""
+    rng = np.random.default_rng(p.tile)
+    for n in [0, 1, 2, 3, 5, 17, 64, 100, 257, 1000, 3001]:
+        for w in (4, 8, 16):
+            if p.tile * w > 131072:
+                continue
+            seed = int(rng.integers(0, 2**63))
+            host = workloads.identity(n, w)
+            assert_same(gpu_shuffle(host, seed, p), oracle_shuffle(host, seed, p), f"n={n} w={w} {p}")
+
+
+def test_config_small_u32_seed42():
+    """2^20 uint32 identity, seed 42, default parameters."""
+    n, w = 1 << 20, 4
+    host = workloads.identity(n, w)
+    p = oracle.default_params(n, w)
+    assert_same(gpu_shuffle(host, 42, p), oracle_shuffle(host, 42, p), "2^20 u32")
+
+
+@pytest.mark.parametrize("n,w", [(100_003, 4), (1 << 22, 4), (3_000_017, 8), (1 << 21, 16), (777_777, 16)])
+def test_default_params_widths(n, w):
+    host = workloads.identity(n, w)
+    p = oracle.default_params(n, w)
+    seed = 0x9E3779B97F4A7C15 ^ n
+    assert_same(gpu_shuffle(host, seed, p), oracle_shuffle(host, seed, p), f"n={n} w={w}")
+
+
+@pytest.mark.parametrize(
+    "n,w,p",
+    [
+        (1_000_000, 4, oracle.Params(1024, 5, 16, 32)),
+        (600_000, 8, oracle.Params(777, 4, 10, 32)),
+        (300_000, 16, oracle.Params(2000, 8, 64, 32)),
+        (2_000_000, 4, oracle.Params(32768, 8, 64, 32)),
+        (500_000, 4, oracle.Params(300, 2, 5, 32)),
+    ],
+)
+def test_multi_level_small_tiles(n, w, p):
+    """Several tiled levels with many movers per level."""
+    host = workloads.identity(n, w)
+    assert_same(gpu_shuffle(host, 12345, p), oracle_shuffle(host, 12345, p), f"n={n} w={w} {p}")
+
+
+def test_stream_ids_and_seeds():
+    n, w = 200_000, 4
+    host = workloads.identity(n, w)
+    p = oracle.default_params(n, w)
+    for seed, sid in [(1, 0), (1, 1), (2**64 - 1, 7), (0, 2**32 - 1)]:
+        assert_same(gpu_shuffle(host, seed, p, sid), oracle_shuffle(host, seed, p, sid), f"seed={seed} sid={sid}")
+
+
+def test_data_independence_on_gpu():
+    n, w = 300_000, 8
+    ident = workloads.identity(n, w)
+    vals = workloads.random_values(n, w, 5)
+    p = oracle.default_params(n, w)
+    perm = gpu_shuffle(ident, 99, p)
+    out = gpu_shuffle(vals, 99, p)
+    assert np.array_equal(out, vals[perm.astype(np.int64)])
+
+
+def test_determinism_and_other_stream():
+    shuf = _lib()
+    n, w = 1 << 20, 4
+    host = workloads.identity(n, w)
+    a = gpu_shuffle(host, 5, None)
+    t = to_dev(host)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        shuf.shuffle_inplace(t, 5, stream=s)
+    s.synchronize()
+    assert np.array_equal(from_dev(t, host), a)
+    assert np.array_equal(gpu_shuffle(host, 5, None), a)
+
+
+def test_batched_matches_single_arrays():
+    shuf = _lib()
+    sizes = workloads.log_uniform_sizes(300, 0, 15, seed=3)
+    offs = workloads.csr_offsets(sizes)
+    host = workloads.batched_identity(sizes)
+    t = to_dev(host)
+    print(f"[gpu] batched arrays={len(sizes)} total={host.size}", flush=True)
+    shuf.shuffle_batched(t, offs, 777)
+    torch.cuda.synchronize()
+    got = from_dev(t, host)
+    for j in range(len(sizes)):
+        a, b = int(offs[j]), int(offs[j + 1])
+        want = oracle_shuffle(host[a:b], 777, oracle.default_params(b - a, 4), stream_id=j)
+        assert_same(got[a:b], want, f"batched array {j} (n={b - a})")
+
+
+def test_stats_report_tiled_levels():
+    shuf = _lib()
+    host = workloads.identity(1 << 21, 4)
+    gpu_shuffle(host, 1, None)
+    st = shuf.last_stats()
+    assert st["tiled_levels"] == 1
+    assert st["movers"] > 0 and st["leaves"] > 0
+
+
+def test_argument_errors_leave_data_untouched():
+    import ctypes
+
+    shuf = _lib()
+    host = workloads.identity(1000, 4)
+    t = to_dev(host)
+    ptr = ctypes.c_void_p(t.data_ptr())
+    P = shuf._Params
+    good = P(32768, 8, 64, 32)
+    null = ctypes.c_void_p(0)
+    cases = [
+        ("shuffle_inplace", (null, 1000, 4, 1, null), shuf.SHUF_EINVAL),
+        ("shuffle_inplace", (ptr, 1000, 3, 1, null), shuf.SHUF_EINVAL),
+        ("shuffle_inplace", (ctypes.c_void_p(t.data_ptr() + 2), 999, 4, 1, null), shuf.SHUF_EINVAL),
+        ("shuffle_inplace", (ptr, 1 << 41, 4, 1, null), shuf.SHUF_EUNSUPPORTED),
+        ("shuffle_inplace_ex", (ptr, 1000, 4, 1, 0, None, null), shuf.SHUF_EINVAL),
+        ("shuffle_inplace_ex", (ptr, 1000, 4, 1, 0, ctypes.byref(P(3, 2, 1, 1)), null), shuf.SHUF_EINVAL),
+        ("shuffle_inplace_ex", (ptr, 1000, 4, 1, 0, ctypes.byref(P(32768, 9, 1, 1)), null), shuf.SHUF_EINVAL),
+        ("shuffle_inplace_ex", (ptr, 1000, 4, 1, 0, ctypes.byref(P(32768, 8, 0, 1)), null), shuf.SHUF_EINVAL),
+        ("shuffle_inplace_ex", (ptr, 1000, 4, 1, 0, ctypes.byref(P(32768, 8, 64, 256)), null), shuf.SHUF_EINVAL),
+        ("shuffle_inplace_ex", (ptr, 1000, 4, 1, 0, ctypes.byref(P(40000, 8, 64, 32)), null), shuf.SHUF_EUNSUPPORTED),
+        ("shuffle_inplace_ex", (ptr, 1000, 4, 1, 0, ctypes.byref(P(32768, 8, 1, 32)), null), shuf.SHUF_EUNSUPPORTED),
+    ]
+    for name, args, code in cases:
+        print(f"[gpu] error case {name} -> {code}", flush=True)
+        assert shuf.raw_call(name, *args) == code
+    offs = (ctypes.c_uint64 * 3)(0, 600, 500)
+    assert shuf.raw_call("shuffle_batched", ptr, offs, 2, 4, 1, null) == shuf.SHUF_EINVAL
+    assert shuf.raw_call("shuffle_batched", ptr, None, 2, 4, 1, null) == shuf.SHUF_EINVAL
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev(t, host), host)
+    # n <= 1 is a successful no-op, even with a NULL pointer
+    assert shuf.raw_call("shuffle_inplace", null, 1, 4, 1, null) == 0
+    assert shuf.raw_call("shuffle_inplace", null, 0, 8, 1, null) == 0

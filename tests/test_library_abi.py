@@ -1,0 +1,67 @@
+"""CPU-side checks of the C ABI library: it loads, exports every function the
+header declares, and its host-only functions behave (no GPU work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ipscshuf.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_][a-z_0-9]*)\s*\(", text, flags=re.M)))
+
+
+def _lib():
+    import paper_2302_03317_amd as shuf
+
+    if not os.path.exists(shuf.LIB_PATH):
+        pytest.skip("library not built")
+    return shuf
+
+
+def test_header_declares_entry_points():
+    names = _declared_functions()
+    for n in ["shuffle_inplace", "shuffle_inplace_ex", "shuffle_batched", "shuf_default_params",
+              "shuffle_strerror", "shuffle_definition_version", "shuffle_last_stats"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    shuf = _lib()
+    lib = ctypes.CDLL(shuf.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_host_only_functions():
+    shuf = _lib()
+    assert shuf.definition_version() == 1
+    assert shuf.strerror(0) == "success"
+    assert "unsupported" in shuf.strerror(-4)
+    for w in (4, 8, 16):
+        p = shuf.default_params(1 << 20, w)
+        # the defaults are part of the definition; the oracle writes them down independently
+        q = oracle.default_params(1 << 20, w)
+        assert (p.tile, p.kmax_log2, p.n0, p.lmax) == (q.tile, q.kmax_log2, q.n0, q.lmax)
+    with pytest.raises(shuf.ShuffleError):
+        shuf.default_params(10, 3)
+
+
+def test_invalid_arguments_rejected_without_gpu():
+    """Argument checks run before any HIP call, so they work on a CPU host."""
+    shuf = _lib()
+    null = ctypes.c_void_p(0)
+    assert shuf.raw_call("shuffle_inplace", null, 10, 4, 1, null) == shuf.SHUF_EINVAL
+    assert shuf.raw_call("shuffle_inplace", null, 10, 5, 1, null) == shuf.SHUF_EINVAL
+    assert shuf.raw_call("shuffle_inplace", null, 1, 4, 1, null) == 0
+    p = shuf._Params(3, 2, 1, 1)
+    assert shuf.raw_call("shuffle_inplace_ex", null, 10, 4, 1, 0, ctypes.byref(p), null) == shuf.SHUF_EINVAL
+    offs = (ctypes.c_uint64 * 3)(0, 5, 4)
+    assert shuf.raw_call("shuffle_batched", null, offs, 2, 4, 1, null) == shuf.SHUF_EINVAL
