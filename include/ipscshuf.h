@@ -47,7 +47,7 @@ extern "C" {
 #define SHUF_EUNSUPPORTED -4 /* valid, but beyond what this implementation handles */
 
 /* Parameters that are part of the permutation's definition.
- *   tile       T: elements one tile holds; tile * elem_bytes <= 131072 and
+ *   tile       T: elements one tile holds; tile * elem_bytes <= 65536 and
  *              tile >= 2^kmax_log2 + 1
  *   kmax_log2  largest bucket-count exponent (k <= 2^kmax_log2), 1..8
  *   n0         base-case size: subproblems of at most n0 elements are
@@ -66,7 +66,7 @@ typedef struct {
 uint32_t shuffle_definition_version(void);
 
 /* Default parameters for n elements of elem_bytes each (4, 8 or 16):
- * tile = 131072 / elem_bytes, kmax_log2 = 8, n0 = 64, lmax = 32.
+ * tile = 65536 / elem_bytes, kmax_log2 = 8, n0 = 64, lmax = 32.
  * Returns SHUF_EINVAL for a null `out` or an unsupported width. */
 int shuf_default_params(uint64_t n, uint32_t elem_bytes, shuf_params_t* out);
 
@@ -118,6 +118,24 @@ typedef struct {
     uint64_t workspace_bytes;
 } shuf_stats_t;
 int shuffle_last_stats(shuf_stats_t* out);
+
+/* Per-kernel timing with HIP events recorded on the caller's stream around
+ * every launch group (instrumentation for benchmarks; it adds one event pair
+ * per launch).  Kinds, in this order: 0 rough pass, 1 level tables,
+ * 2 fix-up gather, 3 fix-up scatter, 4 LDS leaves, 5 sequential fallback.
+ * `bytes` is the algorithmic HBM traffic of the launches: every element the
+ * kernel moves is counted once read and once written.
+ * shuffle_timing_enable(1) clears the accumulators of the current device and
+ * starts timing, (0) stops; shuffle_timing_read fills out[0..5].  Both return
+ * SHUF_EINVAL for a NULL `out`. */
+typedef struct {
+    double ms;
+    uint64_t launches;
+    double bytes;
+} shuf_kernel_time_t;
+#define SHUF_KERNEL_KINDS 6
+int shuffle_timing_enable(int on);
+int shuffle_timing_read(shuf_kernel_time_t* out);
 
 #ifdef __cplusplus
 }

@@ -213,6 +213,6 @@ def position_histogram(n: int, seed0: int, nseeds: int, p: Params) -> np.ndarray
 
 
 def default_params(n: int, elem_bytes: int) -> Params:
-    """The default parameters for (n, elem_bytes): a 128 KiB tile."""
-    tile_bytes = 131072
+    """The default parameters for (n, elem_bytes): a 64 KiB tile."""
+    tile_bytes = 65536
     return Params(tile=tile_bytes // elem_bytes, kmax_log2=8, n0=64, lmax=32)

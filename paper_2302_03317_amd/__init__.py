@@ -52,6 +52,13 @@ class _Stats(ctypes.Structure):
     ]
 
 
+class _KernelTime(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_uint64), ("bytes", ctypes.c_double)]
+
+
+KERNEL_KINDS = ("rough", "tables", "gather", "scatter", "leaf", "fy_fallback")
+
+
 @dataclass(frozen=True)
 class Params:
     """tile: elements per tile; kmax_log2: max bucket-count exponent;
@@ -91,6 +98,10 @@ def lib() -> ctypes.CDLL:
         L.shuffle_strerror.restype = ctypes.c_char_p
         L.shuffle_last_stats.argtypes = [ctypes.POINTER(_Stats)]
         L.shuffle_last_stats.restype = i
+        L.shuffle_timing_enable.argtypes = [i]
+        L.shuffle_timing_enable.restype = i
+        L.shuffle_timing_read.argtypes = [ctypes.POINTER(_KernelTime)]
+        L.shuffle_timing_read.restype = i
         _lib = L
     return _lib
 
@@ -178,6 +189,23 @@ def last_stats() -> dict:
     if rc != SHUF_OK:
         raise ShuffleError(rc, "shuffle_last_stats")
     return {f: int(getattr(s, f)) for f, _ in _Stats._fields_ if f != "reserved"}
+
+
+def timing_enable(on: bool = True) -> None:
+    """Start (and clear) or stop per-kernel HIP-event timing on the current device."""
+    rc = lib().shuffle_timing_enable(1 if on else 0)
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_timing_enable")
+
+
+def timing_read() -> dict:
+    """{kind: {"ms", "launches", "bytes"}} accumulated since timing_enable()."""
+    arr = (_KernelTime * len(KERNEL_KINDS))()
+    rc = lib().shuffle_timing_read(arr)
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_timing_read")
+    return {k: {"ms": arr[i].ms, "launches": int(arr[i].launches), "bytes": arr[i].bytes}
+            for i, k in enumerate(KERNEL_KINDS)}
 
 
 def raw_call(name: str, *args) -> int:

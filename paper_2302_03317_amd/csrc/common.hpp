@@ -7,9 +7,9 @@
 
 namespace ipss {
 
-constexpr int kThreads = 1024;             // threads of a tile / leaf workgroup
+constexpr int kThreads = 512;              // threads of a tile / leaf workgroup
 constexpr int kWaves = kThreads / 64;      // wave64
-constexpr uint32_t kTileBytesMax = 131072; // most bytes of one tile's elements
+constexpr uint32_t kTileBytesMax = 65536;  // most bytes of one tile's elements
 constexpr uint32_t kKmax = 256;            // labels live in one byte
 constexpr uint32_t kChunk = 256;           // tiles per chunk of the table scans
 constexpr uint32_t kLdsBytesMax = 163840;  // LDS of one CU on gfx950
@@ -84,11 +84,11 @@ struct RoughLayout {
 
 __host__ __device__ __forceinline__ RoughLayout rough_layout(uint32_t T, uint32_t w, uint32_t kmax)
 {
-    const uint32_t overlay = align16(T) + kWaves * kmax * 4u;
+    const uint32_t overlay = align16(T) + kWaves * (kmax + 1) * 4u;
     uint32_t stage = align16(T * w);
     if (overlay > stage) stage = align16(overlay);
-    // lo: (kmax+1) u64; qoff, cap, fill, ovt, hot, nblk: (kmax+1) u32 each
-    const uint32_t tables = (kmax + 1) * 8u + 6u * (kmax + 1) * 4u;
+    // lo: (kmax+1) u64; qoff, cap, fill, ovt, hot, nblk: (kmax+1) u32 each; 16 u32 misc
+    const uint32_t tables = (kmax + 1) * 8u + 6u * (kmax + 1) * 4u + 64u;
     return {stage, stage, stage + align16(tables)};
 }
 
@@ -114,7 +114,7 @@ __host__ __device__ __forceinline__ LeafLayout leaf_layout(uint32_t T, uint32_t 
     LeafLayout L;
     L.idx = 0;
     L.lab = align16(T * 2u);
-    L.hist = L.lab + align16(T);
+    L.hist = L.lab + align16(T + 32u);  // labels of whole 16-position blocks, plus slack
     L.segs = L.hist + align16((kWaves + 1) * (kmax + 1) * 4u);
     L.tmpk = L.segs + align16(2u * seg_cap * 4u);
     L.misc = L.tmpk + align16((seg_cap + 1) * 4u);
@@ -154,6 +154,23 @@ __device__ __forceinline__ uint64_t wave_inclusive_sum64(uint64_t v)
         if (static_cast<int>(lane_id()) >= d) v += o;
     }
     return v;
+}
+
+// Lanes of the wave whose KAPPA-bit label equals this lane's, among the lanes
+// in `valid`: one ballot per label bit; the per-bit mask update
+// acc & ~(t ^ m) is a single three-input bit operation.
+template <int KAPPA>
+__device__ __forceinline__ uint64_t match_label_bits(uint32_t l, uint64_t valid)
+{
+    uint32_t lo = static_cast<uint32_t>(valid), hi = static_cast<uint32_t>(valid >> 32);
+#pragma unroll
+    for (int i = 0; i < KAPPA; ++i) {
+        const uint32_t t = static_cast<uint32_t>(static_cast<int32_t>(l << (31 - i)) >> 31);
+        const uint64_t m = __ballot(t != 0);
+        lo = __builtin_amdgcn_bitop3_b32(lo, t, static_cast<uint32_t>(m), 0x90);
+        hi = __builtin_amdgcn_bitop3_b32(hi, t, static_cast<uint32_t>(m >> 32), 0x90);
+    }
+    return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
 // Exclusive prefix sum of a[0..n) in place and a[n] = total; called by one

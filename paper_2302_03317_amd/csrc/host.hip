@@ -78,7 +78,64 @@ struct Context {
         leaves, gfy, err;
     HostBuf h_subs, h_tile_sub, h_chunk_sub, h_bk_sub, h_N, h_total, h_leaves, h_gfy, h_err;
     shuf_stats_t stats{};
+    // timing
+    bool timing = false;
+    shuf_kernel_time_t times[SHUF_KERNEL_KINDS]{};
+    std::vector<hipEvent_t> event_pool;
+    size_t events_used = 0;
+    struct Span {
+        hipEvent_t a, b;
+        int kind;
+        double bytes;
+    };
+    std::vector<Span> spans;
 };
+
+// Event pairs around launch groups when timing is on.
+struct SpanGuard {
+    Context& C;
+    hipStream_t s;
+    int kind;
+    double bytes;
+    hipEvent_t a = nullptr;
+    SpanGuard(Context& c, hipStream_t st, int k, double by) : C(c), s(st), kind(k), bytes(by)
+    {
+        if (!C.timing) return;
+        a = next_event();
+        if (a) (void)hipEventRecord(a, s);
+    }
+    ~SpanGuard()
+    {
+        if (!C.timing || !a) return;
+        hipEvent_t b = next_event();
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        C.spans.push_back({a, b, kind, bytes});
+    }
+    hipEvent_t next_event()
+    {
+        if (C.events_used == C.event_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            C.event_pool.push_back(e);
+        }
+        return C.event_pool[C.events_used++];
+    }
+};
+
+void collect_spans(Context& C)
+{
+    for (const Context::Span& sp : C.spans) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) {
+            C.times[sp.kind].ms += ms;
+            C.times[sp.kind].launches += 1;
+            C.times[sp.kind].bytes += sp.bytes;
+        }
+    }
+    C.spans.clear();
+    C.events_used = 0;
+}
 
 constexpr int kMaxDevices = 64;
 Context g_ctx[kMaxDevices];
@@ -157,6 +214,8 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
     }
     shuf_stats_t st{};
     const uint32_t kmax = 1u << prm.kmax_log2;
+    C.spans.clear();
+    C.events_used = 0;
     HIP_TRY(C.err.ensure(4));
     HIP_TRY(C.h_err.ensure(4));
     HIP_TRY(hipMemsetAsync(C.err.p, 0, 4, stream));
@@ -261,17 +320,31 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
         T.nchunks = nchunks;
         T.nbuckets = nbk;
 
-        HIP_TRY(launch_rough(w, buf, T.subs, T.tile_sub, T.cnt, ntiles, seed, prm, stream));
-        HIP_TRY(launch_tables_sizes(T, stream));
-        HIP_TRY(launch_tables_routes(T, stream));
+        uint64_t level_elems = 0;
+        for (const SubDesc& d : subs) level_elems += d.m;
+        {
+            SpanGuard g(C, stream, 0, 2.0 * level_elems * w);
+            HIP_TRY(launch_rough(w, buf, T.subs, T.tile_sub, T.cnt, ntiles, seed, prm, stream));
+        }
+        {
+            SpanGuard g(C, stream, 1, 0.0);
+            HIP_TRY(launch_tables_sizes(T, stream));
+            HIP_TRY(launch_tables_routes(T, stream));
+        }
         HIP_TRY(hipMemcpyAsync(C.h_N.p, T.N, nbk * 8, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipMemcpyAsync(C.h_total.p, T.total, 8, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         const uint64_t movers = C.h_total.as<uint64_t>()[0];
         HIP_TRY(C.ws.ensure(std::max<uint64_t>(movers, 1) * w));
         T.ws_cap = movers;
-        HIP_TRY(launch_gather(w, buf, static_cast<uint8_t*>(C.ws.p), T, stream));
-        HIP_TRY(launch_scatter(w, buf, static_cast<const uint8_t*>(C.ws.p), T, stream));
+        {
+            SpanGuard g(C, stream, 2, 2.0 * movers * w);
+            HIP_TRY(launch_gather(w, buf, static_cast<uint8_t*>(C.ws.p), T, stream));
+        }
+        {
+            SpanGuard g(C, stream, 3, 2.0 * movers * w);
+            HIP_TRY(launch_scatter(w, buf, static_cast<const uint8_t*>(C.ws.p), T, stream));
+        }
 
         st.tiled_levels++;
         st.tiles += ntiles;
@@ -301,17 +374,24 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
     }
     if (!ld.empty()) {
         HIP_TRY(upload(C.leaves, C.h_leaves, ld, stream));
+        uint64_t elems = 0;
+        for (const LeafDesc& l : ld) elems += l.m;
+        SpanGuard g(C, stream, 4, 2.0 * elems * w);
         HIP_TRY(launch_leaf(w, buf, static_cast<const LeafDesc*>(C.leaves.p), ld.size(), seed, prm,
                             stream));
     }
     if (!fd.empty()) {
         HIP_TRY(upload(C.gfy, C.h_gfy, fd, stream));
+        uint64_t elems = 0;
+        for (const LeafDesc& l : fd) elems += l.m;
+        SpanGuard g(C, stream, 5, 2.0 * elems * w);
         HIP_TRY(launch_fy_global(w, buf, static_cast<const LeafDesc*>(C.gfy.p), fd.size(), seed,
                                  stream));
     }
     HIP_TRY(hipMemcpyAsync(C.h_err.p, C.err.p, 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     if (C.h_err.as<uint32_t>()[0] != 0) return SHUF_EHIP;  // an index check failed in a kernel
+    if (C.timing) collect_spans(C);
     st.leaves = ld.size();
     st.fy_fallback = fd.size();
     C.stats = st;
@@ -407,6 +487,32 @@ const char* shuffle_strerror(int code)
     case SHUF_EUNSUPPORTED: return "unsupported size or parameters";
     default: return "unknown error";
     }
+}
+
+int shuffle_timing_enable(int on)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SHUF_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return SHUF_EUNSUPPORTED;
+    Context& C = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(C.mu);
+    C.timing = on != 0;
+    for (auto& t : C.times) t = shuf_kernel_time_t{};
+    C.spans.clear();
+    C.events_used = 0;
+    return SHUF_OK;
+}
+
+int shuffle_timing_read(shuf_kernel_time_t* out)
+{
+    if (!out) return SHUF_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SHUF_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return SHUF_EUNSUPPORTED;
+    Context& C = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(C.mu);
+    for (int i = 0; i < SHUF_KERNEL_KINDS; ++i) out[i] = C.times[i];
+    return SHUF_OK;
 }
 
 int shuffle_last_stats(shuf_stats_t* out)

@@ -42,43 +42,138 @@ __device__ __forceinline__ uint32_t kappa_in_tile(uint32_t m, const Params& prm)
     return kap < prm.kmax_log2 ? kap : prm.kmax_log2;
 }
 
-// Fisher-Yates on idx[s0, s0 + len): i from len-1 down to 1, partner drawn
-// from [0, i] at position pbase + s0 + i.  One Philox block serves four
-// consecutive positions.
+// Fisher-Yates on idx[s0, s0 + len) (len >= 2): i from len-1 down to 1, the
+// partner drawn from [0, i] at position pbase + s0 + i.  One Philox block
+// serves the four positions 4B..4B+3.  The lanes of a wave run different
+// segments, so each lane starts after o idle steps, o chosen so that every
+// lane enters a new block on the same step: the block is then computed once
+// per four steps for the whole wave.
 __device__ void fy_segment(uint16_t* idx, uint32_t s0, uint32_t len, uint64_t pbase,
                            uint32_t level, const Key& key)
 {
-    uint64_t cached = ~0ull;
+    const uint64_t top = pbase + s0 + len - 1;           // position of the first step
+    const uint32_t o = (3u - static_cast<uint32_t>(top & 3)) & 3u;
+    const uint32_t steps = o + len - 1;
     Word4 v = {0, 0, 0, 0};
-    for (uint32_t i = len - 1; i >= 1; --i) {
-        const uint64_t p = pbase + s0 + i;
-        if ((p >> 2) != cached) {
-            cached = p >> 2;
-            v = fy_block(key, level, cached, 0);
-        }
-        const uint32_t j = fy_draw_from(key, level, p, i + 1, v);
+    for (uint32_t s = 0; s < steps; ++s) {
+        // virtual position top + o - s; a block starts every four steps
+        const uint64_t vp = top + o - s;
+        if ((s & 3) == 0) v = fy_block(key, level, vp >> 2, 0);
+        if (s < o) continue;
+        const uint32_t i = len - 1 - (s - o);
+        const uint32_t j = fy_draw_from(key, level, vp, i + 1, v);
         const uint16_t a = idx[s0 + i];
         idx[s0 + i] = idx[s0 + j];
         idx[s0 + j] = a;
     }
 }
 
-// Match the labels of one round: lanes with the same valid label.
-__device__ __forceinline__ uint64_t match_label(uint32_t l, bool valid, uint32_t kappa)
+// Whole-workgroup stable split of segment [s0, s0 + len) by KAPPA-bit labels;
+// children (start, length) go to out[0..k).
+template <int KAPPA>
+__device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* lab, uint32_t* H,
+                                                uint32_t hs, uint32_t* out, uint32_t s0,
+                                                uint32_t len, uint32_t tid, uint32_t wv,
+                                                uint32_t lane)
 {
-    uint64_t peers = __ballot(valid);
-    for (uint32_t i = 0; i < kappa; ++i) {
-        const bool bit = (l >> i) & 1u;
-        const uint64_t mb = __ballot(bit);
-        peers &= bit ? mb : ~mb;
+    constexpr uint32_t k = 1u << KAPPA, sh = 8 - KAPPA;
+    uint32_t* Htot = H + kWaves * hs;
+    const uint32_t end = s0 + len;
+    const uint32_t per_wave = ((len + kWaves * 64 - 1) / (kWaves * 64)) * 64;
+    const uint32_t rounds = per_wave / 64;
+    const uint32_t first = s0 + wv * per_wave + lane;
+    for (uint32_t j = tid; j < (kWaves + 1) * hs; j += kThreads) H[j] = 0;
+    __syncthreads();
+    uint32_t pk[kRounds];
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+        if (r >= rounds) break;
+        const uint32_t x = first + 64u * r;
+        const bool valid = x < end;
+        uint32_t l = 0, val = 0;
+        if (valid) {
+            l = lab[x] >> sh;
+            val = idx[x];
+        }
+        const uint64_t peers = match_label_bits<KAPPA>(l, __ballot(valid));
+        const uint32_t below = bits_below(peers);
+        uint32_t old = 0;
+        if (valid) old = H[wv * hs + l];
+        if (valid && below == 0) H[wv * hs + l] = old + static_cast<uint32_t>(__popcll(peers));
+        pk[r] = val | ((old + below) << 16);
     }
-    return peers;
+    __syncthreads();
+    for (uint32_t l = tid; l < k; l += kThreads) {
+        uint32_t run = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t v = H[w * hs + l];
+            H[w * hs + l] = run;
+            run += v;
+        }
+        Htot[l] = run;
+    }
+    __syncthreads();
+    if (wv == 0) wave_exclusive_scan(Htot, k);
+    __syncthreads();
+    for (uint32_t l = tid; l < k; l += kThreads)
+        out[l] = seg_pack(s0 + Htot[l], Htot[l + 1] - Htot[l]);
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+        if (r >= rounds) break;
+        const uint32_t x = first + 64u * r;
+        if (x < end) {
+            const uint32_t l = lab[x] >> sh;
+            idx[s0 + Htot[l] + H[wv * hs + l] + (pk[r] >> 16)] = static_cast<uint16_t>(pk[r]);
+        }
+    }
+    __syncthreads();
+}
+
+// One wave's stable split of segment [s0, s0 + len), len <= kWaveSegMax.
+template <int KAPPA>
+__device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, uint32_t* Hw,
+                                           uint32_t* out, uint32_t s0, uint32_t len,
+                                           uint32_t lane)
+{
+    constexpr uint32_t k = 1u << KAPPA, sh = 8 - KAPPA;
+    const uint32_t end = s0 + len;
+    for (uint32_t j = lane; j <= k; j += 64) Hw[j] = 0;
+    const uint32_t rounds = (len + 63) / 64;
+    uint32_t pk[kRounds];
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+        if (r >= rounds) break;
+        const uint32_t x = s0 + 64u * r + lane;
+        const bool valid = x < end;
+        uint32_t l = 0, val = 0;
+        if (valid) {
+            l = lab[x] >> sh;
+            val = idx[x];
+        }
+        const uint64_t peers = match_label_bits<KAPPA>(l, __ballot(valid));
+        const uint32_t below = bits_below(peers);
+        uint32_t old = 0;
+        if (valid) old = Hw[l];
+        if (valid && below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
+        pk[r] = val | ((old + below) << 16);
+    }
+    wave_exclusive_scan(Hw, k);
+    for (uint32_t l = lane; l < k; l += 64) out[l] = seg_pack(s0 + Hw[l], Hw[l + 1] - Hw[l]);
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+        if (r >= rounds) break;
+        const uint32_t x = s0 + 64u * r + lane;
+        if (x < end) {
+            const uint32_t l = lab[x] >> sh;
+            idx[s0 + Hw[l] + (pk[r] >> 16)] = static_cast<uint16_t>(pk[r]);
+        }
+    }
 }
 
 template <typename E, int EMAX>
-__global__ __launch_bounds__(kThreads) void k_leaf(uint8_t* __restrict__ buf,
-                                                   const LeafDesc* __restrict__ leaves,
-                                                   uint64_t seed, Params prm)
+__global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
+                                                      const LeafDesc* __restrict__ leaves,
+                                                      uint64_t seed, Params prm)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
@@ -88,9 +183,8 @@ __global__ __launch_bounds__(kThreads) void k_leaf(uint8_t* __restrict__ buf,
     const uint32_t hs = kmax + 1;  // row stride of the counters
     const LeafLayout LL = leaf_layout(prm.tile, sizeof(E), kmax, prm.n0);
     uint16_t* idx = reinterpret_cast<uint16_t*>(smem + LL.idx);
-    uint8_t* lab = smem + LL.lab;
+    uint8_t* labraw = smem + LL.lab;
     uint32_t* H = reinterpret_cast<uint32_t*>(smem + LL.hist);
-    uint32_t* Htot = H + kWaves * hs;
     uint32_t* cur = reinterpret_cast<uint32_t*>(smem + LL.segs);
     uint32_t* nxt = cur + LL.seg_cap;
     uint32_t* tmpk = reinterpret_cast<uint32_t*>(smem + LL.tmpk);
@@ -100,6 +194,8 @@ __global__ __launch_bounds__(kThreads) void k_leaf(uint8_t* __restrict__ buf,
     E* X = reinterpret_cast<E*>(buf) + ld.elem_off + ld.base;
     const uint64_t pbase = ld.base;
     const Key key = make_key(seed, ld.stream_id);
+    // labraw holds whole label blocks; lab[x] is the label byte of position pbase + x
+    const uint8_t* lab = labraw + (pbase & 15);
 
     E data[EMAX];
 #pragma unroll
@@ -137,19 +233,13 @@ __global__ __launch_bounds__(kThreads) void k_leaf(uint8_t* __restrict__ buf,
             }
             tmpk[i] = kk;
         }
-        // Label bytes of this level for every position of the leaf.
+        // Label bytes of this level: whole 16-byte blocks, aligned.
         {
             const uint64_t b0 = pbase >> 4;
             const uint64_t nb = ((pbase + m - 1) >> 4) - b0 + 1;
             for (uint64_t i = tid; i < nb; i += kThreads) {
-                const uint64_t B = b0 + i;
-                const Word4 v = label_block(key, level, B);
-#pragma unroll
-                for (uint32_t j = 0; j < 16; ++j) {
-                    const uint64_t p = B * 16 + j;
-                    if (p >= pbase && p < pbase + m)
-                        lab[p - pbase] = static_cast<uint8_t>(block_byte(v, j));
-                }
+                const Word4 v = label_block(key, level, b0 + i);
+                *reinterpret_cast<uint4*>(labraw + 16 * i) = make_uint4(v.x, v.y, v.z, v.w);
             }
         }
         __syncthreads();
@@ -161,93 +251,36 @@ __global__ __launch_bounds__(kThreads) void k_leaf(uint8_t* __restrict__ buf,
         for (uint32_t bi = 0; bi < nbig; ++bi) {
             const uint32_t i = misc[2 + bi];
             const uint32_t e = cur[i];
-            const uint32_t s0 = seg_start(e), len = seg_len(e), end = s0 + len;
-            const uint32_t kap = kappa_in_tile(len, prm), k = 1u << kap, sh = 8 - kap;
-            const uint32_t per_wave = ((len + kWaves * 64 - 1) / (kWaves * 64)) * 64;
-            const uint32_t rounds = per_wave / 64;
-            const uint32_t first = s0 + wv * per_wave + lane;
-            for (uint32_t j = tid; j < (kWaves + 1) * hs; j += kThreads) H[j] = 0;
-            __syncthreads();
-            uint32_t pk[kRounds];
-#pragma unroll
-            for (uint32_t r = 0; r < kRounds; ++r) {
-                if (r < rounds) {
-                    const uint32_t x = first + 64u * r;
-                    const bool valid = x < end;
-                    const uint32_t l = valid ? (lab[x] >> sh) : 0u;
-                    const uint64_t peers = match_label(l, valid, kap);
-                    const uint32_t below = bits_below(peers);
-                    uint32_t old = 0;
-                    if (valid) old = H[wv * hs + l];
-                    if (valid && below == 0) H[wv * hs + l] = old + static_cast<uint32_t>(__popcll(peers));
-                    pk[r] = valid ? (static_cast<uint32_t>(idx[x]) | ((old + below) << 16)) : 0u;
-                }
+            const uint32_t s0 = seg_start(e), len = seg_len(e);
+            uint32_t* out = nxt + tmpk[i];
+            switch (kappa_in_tile(len, prm)) {
+            case 1: split_workgroup<1>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 2: split_workgroup<2>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 3: split_workgroup<3>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 4: split_workgroup<4>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 5: split_workgroup<5>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 6: split_workgroup<6>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 7: split_workgroup<7>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            default: split_workgroup<8>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
             }
-            __syncthreads();
-            for (uint32_t l = tid; l < k; l += kThreads) {
-                uint32_t run = 0;
-                for (int w = 0; w < kWaves; ++w) {
-                    const uint32_t v = H[w * hs + l];
-                    H[w * hs + l] = run;
-                    run += v;
-                }
-                Htot[l] = run;
-            }
-            __syncthreads();
-            if (wv == 0) wave_exclusive_scan(Htot, k);
-            __syncthreads();
-            for (uint32_t l = tid; l < k; l += kThreads)
-                nxt[tmpk[i] + l] = seg_pack(s0 + Htot[l], Htot[l + 1] - Htot[l]);
-#pragma unroll
-            for (uint32_t r = 0; r < kRounds; ++r) {
-                if (r < rounds) {
-                    const uint32_t x = first + 64u * r;
-                    if (x < end) {
-                        const uint32_t l = lab[x] >> sh;
-                        idx[s0 + Htot[l] + H[wv * hs + l] + (pk[r] >> 16)] =
-                            static_cast<uint16_t>(pk[r] & 0xFFFFu);
-                    }
-                }
-            }
-            __syncthreads();
         }
 
         // Other splitting segments: one wave each.
         for (uint32_t i = wv; i < nseg; i += kWaves) {
             const uint32_t e = cur[i];
-            const uint32_t s0 = seg_start(e), len = seg_len(e), end = s0 + len;
+            const uint32_t s0 = seg_start(e), len = seg_len(e);
             if (len < 2 || len <= prm.n0 || level >= prm.lmax || len > kWaveSegMax) continue;
-            const uint32_t kap = kappa_in_tile(len, prm), k = 1u << kap, sh = 8 - kap;
             uint32_t* Hw = H + wv * hs;
-            for (uint32_t j = lane; j <= k; j += 64) Hw[j] = 0;
-            const uint32_t rounds = (len + 63) / 64;
-            uint32_t pk[kRounds];
-#pragma unroll
-            for (uint32_t r = 0; r < kRounds; ++r) {
-                if (r < rounds) {
-                    const uint32_t x = s0 + 64u * r + lane;
-                    const bool valid = x < end;
-                    const uint32_t l = valid ? (lab[x] >> sh) : 0u;
-                    const uint64_t peers = match_label(l, valid, kap);
-                    const uint32_t below = bits_below(peers);
-                    uint32_t old = 0;
-                    if (valid) old = Hw[l];
-                    if (valid && below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
-                    pk[r] = valid ? (static_cast<uint32_t>(idx[x]) | ((old + below) << 16)) : 0u;
-                }
-            }
-            wave_exclusive_scan(Hw, k);
-            for (uint32_t l = lane; l < k; l += 64)
-                nxt[tmpk[i] + l] = seg_pack(s0 + Hw[l], Hw[l + 1] - Hw[l]);
-#pragma unroll
-            for (uint32_t r = 0; r < kRounds; ++r) {
-                if (r < rounds) {
-                    const uint32_t x = s0 + 64u * r + lane;
-                    if (x < end) {
-                        const uint32_t l = lab[x] >> sh;
-                        idx[s0 + Hw[l] + (pk[r] >> 16)] = static_cast<uint16_t>(pk[r] & 0xFFFFu);
-                    }
-                }
+            uint32_t* out = nxt + tmpk[i];
+            switch (kappa_in_tile(len, prm)) {
+            case 1: split_wave<1>(idx, lab, Hw, out, s0, len, lane); break;
+            case 2: split_wave<2>(idx, lab, Hw, out, s0, len, lane); break;
+            case 3: split_wave<3>(idx, lab, Hw, out, s0, len, lane); break;
+            case 4: split_wave<4>(idx, lab, Hw, out, s0, len, lane); break;
+            case 5: split_wave<5>(idx, lab, Hw, out, s0, len, lane); break;
+            case 6: split_wave<6>(idx, lab, Hw, out, s0, len, lane); break;
+            case 7: split_wave<7>(idx, lab, Hw, out, s0, len, lane); break;
+            default: split_wave<8>(idx, lab, Hw, out, s0, len, lane); break;
             }
         }
         __syncthreads();
@@ -342,14 +375,17 @@ hipError_t launch_leaf(uint32_t w, uint8_t* buf, const LeafDesc* leaves, uint64_
 
 hipError_t set_leaf_lds_limits()
 {
+    constexpr int E4 = static_cast<int>(kTileBytesMax / (4 * kThreads));
+    constexpr int E8 = static_cast<int>(kTileBytesMax / (8 * kThreads));
+    constexpr int E16 = static_cast<int>(kTileBytesMax / (16 * kThreads));
     hipError_t e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<uint32_t, 32>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<uint32_t, E4>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<uint64_t, 16>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<uint64_t, E8>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<Elem16, 8>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<Elem16, E16>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
 }
 

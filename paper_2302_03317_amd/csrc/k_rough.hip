@@ -9,16 +9,44 @@
 // tile's per-bucket counts go to the level's count table; the fix-up kernels
 // use them to route staged and displaced items.
 //
-// HBM traffic per tile: one read and one write of its elements, both streamed
-// through a staging copy in LDS so that global accesses stay contiguous.
+// Memory path: every piece is one contiguous run in HBM, copied whole into an
+// LDS staging array (direct global-to-LDS loads) and, after the permutation,
+// copied back whole; the ranking works on the staging order.  HBM traffic per
+// tile is one read and one write of its elements.  A tile needs
+// T * w + ~8 KiB of LDS, so two workgroups share a CU and one's memory phase
+// overlaps the other's ranking.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "rng.hpp"
 
 namespace ipss {
 
-template <typename E, int EMAX>
-__global__ __launch_bounds__(kThreads) void k_rough(uint8_t* __restrict__ buf,
+namespace {
+
+// Stable ranks of one wave's rounds for KAPPA-bit labels.  Round r gives lane
+// l the read-order slot first + 64r; pk[r] receives label | rank << 8 where
+// rank counts earlier items of the wave with the same label.
+template <int KAPPA, int R>
+__device__ __forceinline__ void rank_rounds(const uint8_t* lab, uint32_t* Hw, uint32_t first,
+                                            uint32_t ts, uint32_t (&pk)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t q = first + 64u * r;
+        const bool valid = q < ts;
+        uint32_t l = 0;
+        if (valid) l = lab[q];
+        const uint64_t peers = match_label_bits<KAPPA>(l, __ballot(valid));
+        const uint32_t below = bits_below(peers);
+        uint32_t old = 0;
+        if (valid) old = Hw[l];
+        if (valid && below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
+        pk[r] = l | ((old + below) << 8);
+    }
+}
+
+template <typename E, int R>
+__global__ __launch_bounds__(kThreads, 4) void k_rough(uint8_t* __restrict__ buf,
                                                     const SubDesc* __restrict__ subs,
                                                     const uint32_t* __restrict__ tile_sub,
                                                     uint32_t* __restrict__ cnt_tab, uint64_t seed,
@@ -32,10 +60,12 @@ __global__ __launch_bounds__(kThreads) void k_rough(uint8_t* __restrict__ buf,
     const uint32_t kappa = sd.kappa, k = 1u << kappa;
     const uint32_t kmax = 1u << prm.kmax_log2;
     const RoughLayout L = rough_layout(prm.tile, sizeof(E), kmax);
+    constexpr uint32_t kWordsPerElem = sizeof(E) / 4;
 
     E* stage = reinterpret_cast<E*>(smem);
-    uint8_t* lab = smem;                                                    // overlays stage
-    uint32_t* H = reinterpret_cast<uint32_t*>(smem + align16(prm.tile));   // overlays stage
+    uint8_t* lab = smem;                                                  // overlays stage
+    uint16_t* fs = reinterpret_cast<uint16_t*>(smem);                    // overlays lab
+    uint32_t* H = reinterpret_cast<uint32_t*>(smem + align16(prm.tile)); // overlays stage
     uint64_t* lo = reinterpret_cast<uint64_t*>(smem + L.tables);
     uint32_t* qoff = reinterpret_cast<uint32_t*>(lo + kmax + 1);
     uint32_t* cap = qoff + kmax + 1;
@@ -43,6 +73,7 @@ __global__ __launch_bounds__(kThreads) void k_rough(uint8_t* __restrict__ buf,
     uint32_t* ovt = fill + kmax + 1;
     uint32_t* hot = ovt + kmax + 1;
     uint32_t* nblk = hot + kmax + 1;
+    const uint32_t hs = k + 1;  // row stride of the per-wave counters
 
     E* X = reinterpret_cast<E*>(buf) + sd.elem_off + sd.base;
     const uint64_t pbase = sd.base;
@@ -69,6 +100,34 @@ __global__ __launch_bounds__(kThreads) void k_rough(uint8_t* __restrict__ buf,
     const uint32_t ts = qoff[k];
     const uint32_t nblocks = nblk[k];
 
+    // Pieces -> staging, one contiguous run each, straight into LDS.
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(X);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(stage);
+        for (uint32_t b = wv; b < k; b += kWaves) {
+            const uint32_t nw = cap[b] * kWordsPerElem;
+            const uint64_t s0 = lo[b] * kWordsPerElem;
+            const uint32_t d0 = qoff[b] * kWordsPerElem;
+            for (uint32_t j = 0; j < nw; j += 64) {
+                if (j + lane < nw)
+                    __builtin_amdgcn_global_load_lds(src + s0 + j + lane, dst + d0 + j, 4, 0, 0);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
+
+    // Wave wv owns read-order slots [wv * 64R, (wv + 1) * 64R); round r gives
+    // lane l the slot wv * 64R + 64r + l.
+    const uint32_t first = wv * 64u * R + lane;
+    E data[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t q = first + 64u * r;
+        if (q < ts) data[r] = stage[q];
+    }
+    __syncthreads();  // staging is free: labels and per-wave counters overlay it
+
     for (uint32_t i = tid; i < nblocks; i += kThreads) {
         const uint32_t b = upper_index(nblk, k, i);
         const uint64_t p0 = pbase + lo[b];
@@ -84,51 +143,20 @@ __global__ __launch_bounds__(kThreads) void k_rough(uint8_t* __restrict__ buf,
                     static_cast<uint8_t>(block_byte(v, j) >> (8 - kappa));
         }
     }
-    for (uint32_t i = tid; i < kWaves * k; i += kThreads) H[i] = 0;
+    for (uint32_t i = tid; i < kWaves * hs; i += kThreads) H[i] = 0;
     __syncthreads();
 
-    // Wave wv owns read-order slots [wv*per_wave, (wv+1)*per_wave); round r
-    // gives lane l the slot wv*per_wave + 64r + l.
-    const uint32_t per_wave = ((ts + kWaves * 64 - 1) / (kWaves * 64)) * 64;
-    const uint32_t rounds = per_wave / 64;  // <= EMAX: the host keeps T <= EMAX * kThreads
-    const uint32_t first = wv * per_wave + lane;
-
-    E data[EMAX];
-    uint32_t pk[EMAX];
-    uint32_t pb = 0;
-    if (first < ts) pb = upper_index(qoff, k, first);
-#pragma unroll
-    for (int r = 0; r < EMAX; ++r) {
-        if (static_cast<uint32_t>(r) < rounds) {
-            const uint32_t q = first + 64u * r;
-            if (q < ts) {
-                while (qoff[pb + 1] <= q) ++pb;
-                data[r] = X[lo[pb] + (q - qoff[pb])];
-            }
-        }
-    }
-
-    // Stable ranks: labels of one round are matched with kappa ballots; the
-    // wave keeps a running count per label.
-#pragma unroll
-    for (int r = 0; r < EMAX; ++r) {
-        if (static_cast<uint32_t>(r) < rounds) {
-            const uint32_t q = first + 64u * r;
-            const bool valid = q < ts;
-            const uint32_t l = valid ? lab[q] : 0u;
-            uint64_t peers = __ballot(valid);
-            for (uint32_t i = 0; i < kappa; ++i) {
-                const bool bit = (l >> i) & 1u;
-                const uint64_t mb = __ballot(bit);
-                peers &= bit ? mb : ~mb;
-            }
-            const uint32_t below = bits_below(peers);
-            const uint32_t total = static_cast<uint32_t>(__popcll(peers));
-            uint32_t old = 0;
-            if (valid) old = H[wv * k + l];
-            if (valid && below == 0) H[wv * k + l] = old + total;
-            pk[r] = l | ((old + below) << 8);
-        }
+    uint32_t pk[R];
+    uint32_t* Hw = H + wv * hs;
+    switch (kappa) {
+    case 1: rank_rounds<1, R>(lab, Hw, first, ts, pk); break;
+    case 2: rank_rounds<2, R>(lab, Hw, first, ts, pk); break;
+    case 3: rank_rounds<3, R>(lab, Hw, first, ts, pk); break;
+    case 4: rank_rounds<4, R>(lab, Hw, first, ts, pk); break;
+    case 5: rank_rounds<5, R>(lab, Hw, first, ts, pk); break;
+    case 6: rank_rounds<6, R>(lab, Hw, first, ts, pk); break;
+    case 7: rank_rounds<7, R>(lab, Hw, first, ts, pk); break;
+    default: rank_rounds<8, R>(lab, Hw, first, ts, pk); break;
     }
     __syncthreads();
 
@@ -136,8 +164,8 @@ __global__ __launch_bounds__(kThreads) void k_rough(uint8_t* __restrict__ buf,
     for (uint32_t l = tid; l < k; l += kThreads) {
         uint32_t run = 0;
         for (int w = 0; w < kWaves; ++w) {
-            const uint32_t v = H[w * k + l];
-            H[w * k + l] = run;
+            const uint32_t v = H[w * hs + l];
+            H[w * hs + l] = run;
             run += v;
         }
         cnt_tab[sd.tab_off + t * k + l] = run;
@@ -151,46 +179,58 @@ __global__ __launch_bounds__(kThreads) void k_rough(uint8_t* __restrict__ buf,
     if (wv == 1) wave_exclusive_scan(hot, k);
     __syncthreads();
 
+    // Free slots of the pieces, in order, as a list (the label area is dead).
+    const uint32_t nfree = hot[k];
+    const bool use_list = nfree <= prm.tile / 2;
+    if (use_list) {
+        for (uint32_t b = wv; b < k; b += kWaves) {
+            const uint32_t base = hot[b], f0 = qoff[b] + fill[b], nh = cap[b] - fill[b];
+            for (uint32_t j = lane; j < nh; j += 64) fs[base + j] = static_cast<uint16_t>(f0 + j);
+        }
+    }
+    __syncthreads();
+
     // Destination slot in read order: placed items at the front of their
     // label's piece; staged items, ordered by (label, rank), into the free
     // slots of the pieces taken in order.
 #pragma unroll
-    for (int r = 0; r < EMAX; ++r) {
-        if (static_cast<uint32_t>(r) < rounds) {
-            const uint32_t q = first + 64u * r;
-            if (q < ts) {
-                const uint32_t l = pk[r] & 0xFFu;
-                const uint32_t rr = H[wv * k + l] + (pk[r] >> 8);
-                uint32_t slot;
-                if (rr < cap[l]) {
-                    slot = qoff[l] + rr;
+    for (int r = 0; r < R; ++r) {
+        const uint32_t q = first + 64u * r;
+        if (q < ts) {
+            const uint32_t l = pk[r] & 0xFFu;
+            const uint32_t rr = H[wv * hs + l] + (pk[r] >> 8);
+            uint32_t slot;
+            if (rr < cap[l]) {
+                slot = qoff[l] + rr;
+            } else {
+                const uint32_t s = ovt[l] + (rr - cap[l]);
+                if (use_list) {
+                    slot = fs[s];
                 } else {
-                    const uint32_t s = ovt[l] + (rr - cap[l]);
                     const uint32_t bb = upper_index(hot, k, s);
                     slot = qoff[bb] + fill[bb] + (s - hot[bb]);
                 }
-                pk[r] = slot;
             }
+            pk[r] = slot;
         }
     }
-    __syncthreads();  // labels and per-wave counts are dead from here on
+    __syncthreads();  // labels, free list and counters are dead from here on
 #pragma unroll
-    for (int r = 0; r < EMAX; ++r) {
-        if (static_cast<uint32_t>(r) < rounds) {
-            const uint32_t q = first + 64u * r;
-            if (q < ts) stage[pk[r]] = data[r];
-        }
+    for (int r = 0; r < R; ++r) {
+        const uint32_t q = first + 64u * r;
+        if (q < ts) stage[pk[r]] = data[r];
     }
     __syncthreads();
-    if (first < ts) pb = upper_index(qoff, k, first);
-#pragma unroll
-    for (int r = 0; r < EMAX; ++r) {
-        if (static_cast<uint32_t>(r) < rounds) {
-            const uint32_t q = first + 64u * r;
-            if (q < ts) {
-                while (qoff[pb + 1] <= q) ++pb;
-                X[lo[pb] + (q - qoff[pb])] = stage[q];
-            }
+
+    // Staging -> pieces, one contiguous run each.
+    {
+        uint32_t* dst = reinterpret_cast<uint32_t*>(X);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(stage);
+        for (uint32_t b = wv; b < k; b += kWaves) {
+            const uint32_t nw = cap[b] * kWordsPerElem;
+            const uint64_t d0 = lo[b] * kWordsPerElem;
+            const uint32_t s0 = qoff[b] * kWordsPerElem;
+            for (uint32_t j = lane; j < nw; j += 64) dst[d0 + j] = src[s0 + j];
         }
     }
 }
@@ -200,13 +240,15 @@ hipError_t launch_rough_t(uint8_t* buf, const SubDesc* subs, const uint32_t* til
                           uint32_t* cnt_tab, uint64_t ntiles, uint64_t seed, const Params& prm,
                           hipStream_t stream)
 {
-    constexpr int EMAX = static_cast<int>(kTileBytesMax / (sizeof(E) * kThreads));
+    constexpr int R = static_cast<int>(kTileBytesMax / (sizeof(E) * kThreads));
     const RoughLayout L = rough_layout(prm.tile, sizeof(E), 1u << prm.kmax_log2);
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_rough<E, EMAX>), dim3(static_cast<uint32_t>(ntiles)), dim3(kThreads),
+    hipLaunchKernelGGL((k_rough<E, R>), dim3(static_cast<uint32_t>(ntiles)), dim3(kThreads),
                        L.total, stream, buf, subs, tile_sub, cnt_tab, seed, prm);
     return hipGetLastError();
 }
+
+}  // namespace
 
 hipError_t launch_rough(uint32_t w, uint8_t* buf, const SubDesc* subs, const uint32_t* tile_sub,
                         uint32_t* cnt_tab, uint64_t ntiles, uint64_t seed, const Params& prm,
@@ -222,14 +264,17 @@ hipError_t launch_rough(uint32_t w, uint8_t* buf, const SubDesc* subs, const uin
 
 hipError_t set_rough_lds_limits()
 {
+    constexpr int R4 = static_cast<int>(kTileBytesMax / (4 * kThreads));
+    constexpr int R8 = static_cast<int>(kTileBytesMax / (8 * kThreads));
+    constexpr int R16 = static_cast<int>(kTileBytesMax / (16 * kThreads));
     hipError_t e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<uint32_t, 32>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<uint32_t, R4>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<uint64_t, 16>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<uint64_t, R8>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<Elem16, 8>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<Elem16, R16>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
 }
 

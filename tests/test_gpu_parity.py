@@ -77,7 +77,7 @@ def test_tiny_parameters_sweep(p):
     rng = np.random.default_rng(p.tile)
     for n in [0, 1, 2, 3, 5, 17, 64, 100, 257, 1000, 3001]:
         for w in (4, 8, 16):
-            if p.tile * w > 131072:
+            if p.tile * w > 65536:
                 continue
             seed = int(rng.integers(0, 2**63))
             host = workloads.identity(n, w)
@@ -106,7 +106,7 @@ def test_default_params_widths(n, w):
         (1_000_000, 4, oracle.Params(1024, 5, 16, 32)),
         (600_000, 8, oracle.Params(777, 4, 10, 32)),
         (300_000, 16, oracle.Params(2000, 8, 64, 32)),
-        (2_000_000, 4, oracle.Params(32768, 8, 64, 32)),
+        (2_000_000, 4, oracle.Params(16384, 8, 64, 32)),
         (500_000, 4, oracle.Params(300, 2, 5, 32)),
     ],
 )
