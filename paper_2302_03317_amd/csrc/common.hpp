@@ -156,16 +156,18 @@ __device__ __forceinline__ uint64_t wave_inclusive_sum64(uint64_t v)
     return v;
 }
 
-// Lanes of the wave whose KAPPA-bit label equals this lane's, among the lanes
-// in `valid`: one ballot per label bit; the per-bit mask update
-// acc & ~(t ^ m) is a single three-input bit operation.
+// Lanes of the wave whose KAPPA-bit label equals this lane's, among the
+// active lanes: one ballot per label bit; the per-bit mask update
+// acc & ~(t ^ m) is a single three-input bit operation.  Call it from code
+// where exactly the lanes holding a valid label are active.
 template <int KAPPA>
-__device__ __forceinline__ uint64_t match_label_bits(uint32_t l, uint64_t valid)
+__device__ __forceinline__ uint64_t match_label_bits(uint32_t l)
 {
-    uint32_t lo = static_cast<uint32_t>(valid), hi = static_cast<uint32_t>(valid >> 32);
+    const uint64_t active = __builtin_amdgcn_read_exec();
+    uint32_t lo = static_cast<uint32_t>(active), hi = static_cast<uint32_t>(active >> 32);
 #pragma unroll
     for (int i = 0; i < KAPPA; ++i) {
-        const uint32_t t = static_cast<uint32_t>(static_cast<int32_t>(l << (31 - i)) >> 31);
+        const uint32_t t = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(l), i, 1));
         const uint64_t m = __ballot(t != 0);
         lo = __builtin_amdgcn_bitop3_b32(lo, t, static_cast<uint32_t>(m), 0x90);
         hi = __builtin_amdgcn_bitop3_b32(hi, t, static_cast<uint32_t>(m >> 32), 0x90);

@@ -48,6 +48,32 @@ struct DevBuf {
     }
 };
 
+// Grow a device buffer to `bytes`, keeping its first `used` bytes.
+hipError_t grow_keep(DevBuf& d, size_t bytes, size_t used, hipStream_t s)
+{
+    if (bytes <= d.cap && d.p) return hipSuccess;
+    void* np = nullptr;
+    const size_t want = std::max<size_t>(bytes + bytes / 2, 4096);
+    hipError_t e = hipMalloc(&np, want);
+    if (e != hipSuccess) return e;
+    if (d.p && used) {
+        e = hipMemcpyAsync(np, d.p, used, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            (void)hipFree(np);
+            return e;
+        }
+    }
+    if (d.p) {
+        e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipFree(d.p);
+        if (e != hipSuccess) return e;
+    }
+    d.p = np;
+    d.cap = want;
+    return hipSuccess;
+}
+
 struct HostBuf {
     void* p = nullptr;
     size_t cap = 0;
@@ -75,8 +101,9 @@ struct Context {
     std::mutex mu;
     bool init = false;
     DevBuf subs, tile_sub, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, total, ws,
-        leaves, gfy, err;
-    HostBuf h_subs, h_tile_sub, h_chunk_sub, h_bk_sub, h_N, h_total, h_leaves, h_gfy, h_err;
+        leaves, big, gfy, err, counters;
+    HostBuf h_subs, h_tile_sub, h_chunk_sub, h_bk_sub, h_total, h_leaves, h_big, h_gfy, h_err,
+        h_counters;
     shuf_stats_t stats{};
     // timing
     bool timing = false;
@@ -214,27 +241,42 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
     }
     shuf_stats_t st{};
     const uint32_t kmax = 1u << prm.kmax_log2;
+    const uint64_t tile_limit = prm.tile - kmax;  // subproblems up to this size finish in LDS
     C.spans.clear();
     C.events_used = 0;
     HIP_TRY(C.err.ensure(4));
     HIP_TRY(C.h_err.ensure(4));
     HIP_TRY(hipMemsetAsync(C.err.p, 0, 4, stream));
-    std::vector<HostSub> cur, leaves, gfy;
-    for (const ArraySpec& a : arrays)
-        if (a.n >= 2) cur.push_back({a.elem_off, 0, a.n, 0, a.stream_id});
+    HIP_TRY(C.counters.ensure(24));
+    HIP_TRY(C.h_counters.ensure(24));
+    HIP_TRY(C.total.ensure(8));
+    HIP_TRY(C.h_total.ensure(8));
+
+    // Roots: arrays that fit a tile are leaves right away.
+    std::vector<LeafDesc> root_leaves, gfy;
+    std::vector<HostSub> cur;
+    for (const ArraySpec& a : arrays) {
+        if (a.n < 2) continue;
+        if (a.n > tile_limit) cur.push_back({a.elem_off, 0, a.n, 0, a.stream_id});
+        else root_leaves.push_back({a.elem_off, 0, a.n, 0, a.stream_id});
+    }
+    uint64_t nleaves = root_leaves.size();
+    HIP_TRY(upload(C.leaves, C.h_leaves, root_leaves, stream));
+    unsigned long long* hc = C.h_counters.as<unsigned long long>();
+    hc[0] = nleaves;
+    hc[1] = 0;
+    hc[2] = 0;
+    for (const LeafDesc& l : root_leaves) hc[2] += l.m;
+    uint64_t leaf_elems = hc[2];
+    HIP_TRY(hipMemcpyAsync(C.counters.p, hc, 24, hipMemcpyHostToDevice, stream));
 
     std::vector<SubDesc> subs;
     std::vector<uint32_t> tile_sub, chunk_sub, bk_sub;
     while (!cur.empty()) {
         std::vector<HostSub> tiled;
         for (const HostSub& s : cur) {
-            if (s.m <= 1) continue;
-            if (s.m > prm.tile - kmax) {
-                if (s.m <= prm.n0 || s.level >= prm.lmax) gfy.push_back(s);
-                else tiled.push_back(s);
-            } else {
-                leaves.push_back(s);
-            }
+            if (s.m <= prm.n0 || s.level >= prm.lmax) gfy.push_back({s.elem_off, s.base, s.m, s.level, s.stream_id});
+            else tiled.push_back(s);
         }
         cur.clear();
         if (tiled.empty()) break;
@@ -273,12 +315,14 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
         tile_sub.resize(ntiles);
         chunk_sub.resize(nchunks);
         bk_sub.resize(nbk);
+        uint64_t level_elems = 0;
         for (uint32_t i = 0; i < nsub; ++i) {
             const SubDesc& d = subs[i];
             std::fill(tile_sub.begin() + d.tile_off, tile_sub.begin() + d.tile_off + d.tiles, i);
             const uint64_t nch = (d.tiles + kChunk - 1) / kChunk;
             std::fill(chunk_sub.begin() + d.chunk_off, chunk_sub.begin() + d.chunk_off + nch, i);
             std::fill(bk_sub.begin() + d.bk_off, bk_sub.begin() + d.bk_off + (1u << d.kappa), i);
+            level_elems += d.m;
         }
         HIP_TRY(upload(C.subs, C.h_subs, subs, stream));
         HIP_TRY(upload(C.tile_sub, C.h_tile_sub, tile_sub, stream));
@@ -294,9 +338,9 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
         HIP_TRY(C.M.ensure(nbk * 8));
         HIP_TRY(C.K.ensure(nbk * 8));
         HIP_TRY(C.MB.ensure(nbk * 8));
-        HIP_TRY(C.total.ensure(8));
-        HIP_TRY(C.h_N.ensure(nbk * 8));
-        HIP_TRY(C.h_total.ensure(8));
+        HIP_TRY(grow_keep(C.leaves, (nleaves + nbk) * sizeof(LeafDesc), nleaves * sizeof(LeafDesc),
+                          stream));
+        HIP_TRY(C.big.ensure(nbk * sizeof(LeafDesc)));
 
         LevelTables T{};
         T.subs = static_cast<const SubDesc*>(C.subs.p);
@@ -320,8 +364,6 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
         T.nchunks = nchunks;
         T.nbuckets = nbk;
 
-        uint64_t level_elems = 0;
-        for (const SubDesc& d : subs) level_elems += d.m;
         {
             SpanGuard g(C, stream, 0, 2.0 * level_elems * w);
             HIP_TRY(launch_rough(w, buf, T.subs, T.tile_sub, T.cnt, ntiles, seed, prm, stream));
@@ -330,11 +372,32 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
             SpanGuard g(C, stream, 1, 0.0);
             HIP_TRY(launch_tables_sizes(T, stream));
             HIP_TRY(launch_tables_routes(T, stream));
+            unsigned long long* dc = static_cast<unsigned long long*>(C.counters.p);
+            HIP_TRY(hipMemsetAsync(dc + 1, 0, 8, stream));
+            HIP_TRY(launch_children(T, static_cast<uint32_t>(tile_limit),
+                                    static_cast<LeafDesc*>(C.leaves.p),
+                                    static_cast<LeafDesc*>(C.big.p), dc, stream));
         }
-        HIP_TRY(hipMemcpyAsync(C.h_N.p, T.N, nbk * 8, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipMemcpyAsync(C.h_total.p, T.total, 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(hc, C.counters.p, 24, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         const uint64_t movers = C.h_total.as<uint64_t>()[0];
+        nleaves = hc[0];
+        leaf_elems = hc[2];
+        const uint64_t nbig = hc[1];
+        if (nbig) {
+            HIP_TRY(C.h_big.ensure(nbig * sizeof(LeafDesc)));
+            HIP_TRY(hipMemcpyAsync(C.h_big.p, C.big.p, nbig * sizeof(LeafDesc),
+                                   hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            const LeafDesc* bl = C.h_big.as<LeafDesc>();
+            for (uint64_t i = 0; i < nbig; ++i)
+                cur.push_back({bl[i].elem_off, bl[i].base, bl[i].m, bl[i].level, bl[i].stream_id});
+            // the device appends in no particular order; plan in position order
+            std::sort(cur.begin(), cur.end(), [](const HostSub& a, const HostSub& b) {
+                return a.elem_off != b.elem_off ? a.elem_off < b.elem_off : a.base < b.base;
+            });
+        }
         HIP_TRY(C.ws.ensure(std::max<uint64_t>(movers, 1) * w));
         T.ws_cap = movers;
         {
@@ -345,55 +408,33 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
             SpanGuard g(C, stream, 3, 2.0 * movers * w);
             HIP_TRY(launch_scatter(w, buf, static_cast<const uint8_t*>(C.ws.p), T, stream));
         }
-
         st.tiled_levels++;
         st.tiles += ntiles;
         st.movers += movers;
         st.workspace_bytes = std::max<uint64_t>(st.workspace_bytes, movers * w);
-
-        const uint64_t* hN = C.h_N.as<uint64_t>();
-        for (uint32_t i = 0; i < nsub; ++i) {
-            const SubDesc& d = subs[i];
-            uint64_t run = 0;
-            for (uint32_t b = 0; b < (1u << d.kappa); ++b) {
-                const uint64_t nb = hN[d.bk_off + b];
-                cur.push_back({d.elem_off, d.base + run, nb, d.level + 1, d.stream_id});
-                run += nb;
-            }
-            if (run != d.m) return SHUF_EHIP;  // counts must add up to the subproblem
-        }
     }
 
-    std::vector<LeafDesc> ld;
-    ld.reserve(leaves.size());
-    for (const HostSub& s : leaves) ld.push_back({s.elem_off, s.base, s.m, s.level, s.stream_id});
-    std::vector<LeafDesc> fd;
-    for (const HostSub& s : gfy) {
-        if (s.m > 0xFFFFFFFFull) return SHUF_EUNSUPPORTED;
-        fd.push_back({s.elem_off, s.base, s.m, s.level, s.stream_id});
-    }
-    if (!ld.empty()) {
-        HIP_TRY(upload(C.leaves, C.h_leaves, ld, stream));
-        uint64_t elems = 0;
-        for (const LeafDesc& l : ld) elems += l.m;
-        SpanGuard g(C, stream, 4, 2.0 * elems * w);
-        HIP_TRY(launch_leaf(w, buf, static_cast<const LeafDesc*>(C.leaves.p), ld.size(), seed, prm,
+    for (const LeafDesc& f : gfy)
+        if (f.m > 0xFFFFFFFFull) return SHUF_EUNSUPPORTED;
+    if (nleaves) {
+        SpanGuard g(C, stream, 4, 2.0 * static_cast<double>(leaf_elems) * w);
+        HIP_TRY(launch_leaf(w, buf, static_cast<const LeafDesc*>(C.leaves.p), nleaves, seed, prm,
                             stream));
     }
-    if (!fd.empty()) {
-        HIP_TRY(upload(C.gfy, C.h_gfy, fd, stream));
+    if (!gfy.empty()) {
+        HIP_TRY(upload(C.gfy, C.h_gfy, gfy, stream));
         uint64_t elems = 0;
-        for (const LeafDesc& l : fd) elems += l.m;
+        for (const LeafDesc& l : gfy) elems += l.m;
         SpanGuard g(C, stream, 5, 2.0 * elems * w);
-        HIP_TRY(launch_fy_global(w, buf, static_cast<const LeafDesc*>(C.gfy.p), fd.size(), seed,
+        HIP_TRY(launch_fy_global(w, buf, static_cast<const LeafDesc*>(C.gfy.p), gfy.size(), seed,
                                  stream));
     }
     HIP_TRY(hipMemcpyAsync(C.h_err.p, C.err.p, 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     if (C.h_err.as<uint32_t>()[0] != 0) return SHUF_EHIP;  // an index check failed in a kernel
     if (C.timing) collect_spans(C);
-    st.leaves = ld.size();
-    st.fy_fallback = fd.size();
+    st.leaves = nleaves;
+    st.fy_fallback = gfy.size();
     C.stats = st;
     return SHUF_OK;
 }

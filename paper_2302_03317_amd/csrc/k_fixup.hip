@@ -208,6 +208,25 @@ __global__ __launch_bounds__(kTabThreads) void k_chunk_route_prefix(LevelTables 
     }
 }
 
+// ---- children of the level: leaves and subproblems that need another tiled level ----
+__global__ __launch_bounds__(kTabThreads) void k_children(LevelTables T, uint32_t tile_limit,
+                                                          LeafDesc* leaves, LeafDesc* big,
+                                                          unsigned long long* counters)
+{
+    const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * kTabThreads + threadIdx.x;
+    if (gb >= T.nbuckets) return;
+    const SubDesc sd = T.subs[T.bk_sub[gb]];
+    const uint64_t n = T.N[gb];
+    if (n <= 1) return;
+    const LeafDesc c{sd.elem_off, sd.base + T.S[gb], n, sd.level + 1, sd.stream_id};
+    if (n <= tile_limit) {
+        leaves[atomicAdd(&counters[0], 1ull)] = c;
+        atomicAdd(&counters[2], static_cast<unsigned long long>(n));
+    } else {
+        big[atomicAdd(&counters[1], 1ull)] = c;
+    }
+}
+
 // ---- gather: movers of one tile into the workspace ----
 template <typename E>
 __global__ __launch_bounds__(kTabThreads) void k_gather(uint8_t* __restrict__ buf,
@@ -348,6 +367,16 @@ hipError_t launch_tables_routes(const LevelTables& t, hipStream_t stream)
     hipLaunchKernelGGL(k_workspace_bases, dim3(1), dim3(1024), 0, stream, t);
     hipLaunchKernelGGL(k_chunk_route_prefix, dim3(static_cast<uint32_t>(t.nchunks)),
                        dim3(kTabThreads), 0, stream, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_children(const LevelTables& t, uint32_t tile_limit, LeafDesc* leaves,
+                           LeafDesc* big, unsigned long long* counters, hipStream_t stream)
+{
+    if (t.nbuckets == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_children,
+                       dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads - 1) / kTabThreads)),
+                       dim3(kTabThreads), 0, stream, t, tile_limit, leaves, big, counters);
     return hipGetLastError();
 }
 

@@ -89,18 +89,16 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
     for (uint32_t r = 0; r < kRounds; ++r) {
         if (r >= rounds) break;
         const uint32_t x = first + 64u * r;
-        const bool valid = x < end;
-        uint32_t l = 0, val = 0;
-        if (valid) {
-            l = lab[x] >> sh;
-            val = idx[x];
+        uint32_t v = 0;
+        if (x < end) {
+            const uint32_t l = lab[x] >> sh;
+            const uint64_t peers = match_label_bits<KAPPA>(l);
+            const uint32_t below = bits_below(peers);
+            const uint32_t old = H[wv * hs + l];
+            if (below == 0) H[wv * hs + l] = old + static_cast<uint32_t>(__popcll(peers));
+            v = static_cast<uint32_t>(idx[x]) | ((old + below) << 16);
         }
-        const uint64_t peers = match_label_bits<KAPPA>(l, __ballot(valid));
-        const uint32_t below = bits_below(peers);
-        uint32_t old = 0;
-        if (valid) old = H[wv * hs + l];
-        if (valid && below == 0) H[wv * hs + l] = old + static_cast<uint32_t>(__popcll(peers));
-        pk[r] = val | ((old + below) << 16);
+        pk[r] = v;
     }
     __syncthreads();
     for (uint32_t l = tid; l < k; l += kThreads) {
@@ -144,18 +142,16 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
     for (uint32_t r = 0; r < kRounds; ++r) {
         if (r >= rounds) break;
         const uint32_t x = s0 + 64u * r + lane;
-        const bool valid = x < end;
-        uint32_t l = 0, val = 0;
-        if (valid) {
-            l = lab[x] >> sh;
-            val = idx[x];
+        uint32_t v = 0;
+        if (x < end) {
+            const uint32_t l = lab[x] >> sh;
+            const uint64_t peers = match_label_bits<KAPPA>(l);
+            const uint32_t below = bits_below(peers);
+            const uint32_t old = Hw[l];
+            if (below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
+            v = static_cast<uint32_t>(idx[x]) | ((old + below) << 16);
         }
-        const uint64_t peers = match_label_bits<KAPPA>(l, __ballot(valid));
-        const uint32_t below = bits_below(peers);
-        uint32_t old = 0;
-        if (valid) old = Hw[l];
-        if (valid && below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
-        pk[r] = val | ((old + below) << 16);
+        pk[r] = v;
     }
     wave_exclusive_scan(Hw, k);
     for (uint32_t l = lane; l < k; l += 64) out[l] = seg_pack(s0 + Hw[l], Hw[l + 1] - Hw[l]);
@@ -219,7 +215,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
         __syncthreads();
 
         // Classify the segments; base-case segments run Fisher-Yates now.
-        for (uint32_t i = tid; i < nseg; i += kThreads) {
+        // Segment i goes to lane (i / kWaves) % 64 of wave i % kWaves, so that
+        // the sequential Fisher-Yates work is spread over all waves.
+        for (uint32_t base = 0; base < nseg; base += kThreads) {
+            const uint32_t i = base + lane * kWaves + wv;
+            if (i >= nseg) continue;
             const uint32_t e = cur[i];
             const uint32_t s0 = seg_start(e), len = seg_len(e);
             uint32_t kk = 0;

@@ -33,15 +33,16 @@ __device__ __forceinline__ void rank_rounds(const uint8_t* lab, uint32_t* Hw, ui
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t q = first + 64u * r;
-        const bool valid = q < ts;
-        uint32_t l = 0;
-        if (valid) l = lab[q];
-        const uint64_t peers = match_label_bits<KAPPA>(l, __ballot(valid));
-        const uint32_t below = bits_below(peers);
-        uint32_t old = 0;
-        if (valid) old = Hw[l];
-        if (valid && below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
-        pk[r] = l | ((old + below) << 8);
+        uint32_t v = 0;
+        if (q < ts) {
+            const uint32_t l = lab[q];
+            const uint64_t peers = match_label_bits<KAPPA>(l);
+            const uint32_t below = bits_below(peers);
+            const uint32_t old = Hw[l];
+            if (below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
+            v = l | ((old + below) << 8);
+        }
+        pk[r] = v;
     }
 }
 

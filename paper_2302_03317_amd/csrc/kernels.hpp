@@ -40,6 +40,13 @@ struct LevelTables {
     uint64_t nsubs, ntiles, nchunks, nbuckets;
 };
 
+// Children of a tiled level: those that fit a tile are appended to the leaf
+// list (leaves[counters[0]++], counters[2] += elements), larger ones to the
+// `big` list (big[counters[1]++]); children of at most one element are done.
+// The order of either list does not affect the result.
+hipError_t launch_children(const LevelTables& t, uint32_t tile_limit, LeafDesc* leaves,
+                           LeafDesc* big, unsigned long long* counters, hipStream_t stream);
+
 // Counts -> final sizes and starts; movers, kept prefixes; workspace bases.
 hipError_t launch_tables_sizes(const LevelTables& t, hipStream_t stream);
 hipError_t launch_tables_routes(const LevelTables& t, hipStream_t stream);
