@@ -84,6 +84,8 @@ def lib():
         L.css_lemire_step.restype = ctypes.c_int
         L.css_lemire_histogram.argtypes = [u64, vp]
         L.css_lemire_histogram.restype = None
+        L.css_lemire16_histogram.argtypes = [u32, vp]
+        L.css_lemire16_histogram.restype = None
         L.css_kappa.argtypes = [u64, ctypes.c_int, ctypes.POINTER(_CParams)]
         L.css_kappa.restype = u32
         L.css_check_params.argtypes = [ctypes.POINTER(_CParams)]
@@ -139,6 +141,12 @@ def lemire_step(word: int, bound: int):
 def lemire_histogram(bound: int) -> np.ndarray:
     counts = np.zeros(bound, dtype=np.uint64)
     lib().css_lemire_histogram(bound, counts.ctypes.data)
+    return counts
+
+
+def lemire16_histogram(bound: int) -> np.ndarray:
+    counts = np.zeros(bound, dtype=np.uint64)
+    lib().css_lemire16_histogram(bound, counts.ctypes.data)
     return counts
 
 

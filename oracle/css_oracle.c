@@ -122,11 +122,30 @@ void css_lemire_histogram(uint64_t bound, uint64_t* counts)
             counts[r]++;
 }
 
-/* One block of four 32-bit words serves four consecutive positions; a
- * rejected word is replaced by the same word of the block with the next
- * attempt number. */
+/* Bounds up to 2^16 ("short" draws): one Philox block serves eight
+ * consecutive positions, 16 bits each (the low half of a word before the
+ * high half), tag purpose 3; Lemire's rule on 16-bit words: x in [0, 2^16),
+ * x*s accepted iff its low 16 bits are at least 2^16 mod s, draw = x*s >> 16.
+ * Larger bounds ("long" draws): one block serves four positions, 32 bits
+ * each, tag purpose 2, Lemire's rule on 32-bit words.  A rejected word is
+ * replaced by the same word of the block with the next attempt number. */
+#define PURPOSE_FY_SHORT 3u
+
 uint64_t css_draw(uint64_t seed, uint32_t stream_id, uint32_t level, uint64_t pos, uint64_t bound)
 {
+    if (bound <= 0x10000u) {
+        const uint32_t threshold = (uint32_t)(0x10000u % bound);
+        for (uint32_t attempt = 0;; ++attempt) {
+            uint32_t x[4];
+            philox_for(seed, stream_id, pos >> 3,
+                       level | (PURPOSE_FY_SHORT << 8) | ((attempt & 0xFFFFu) << 16), x);
+            uint32_t h = (uint32_t)(pos & 7);
+            uint32_t word16 = (x[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
+            uint32_t prod = word16 * (uint32_t)bound;
+            if ((prod & 0xFFFFu) >= threshold)
+                return prod >> 16;
+        }
+    }
     for (uint32_t attempt = 0;; ++attempt) {
         uint32_t x[4];
         philox_for(seed, stream_id, pos >> 2,
@@ -134,6 +153,17 @@ uint64_t css_draw(uint64_t seed, uint32_t stream_id, uint32_t level, uint64_t po
         uint64_t r;
         if (lemire_accept(x[pos & 3], bound, lemire_threshold(bound), &r))
             return r;
+    }
+}
+
+/* Exhaustive check helper for the 16-bit rule: counts[r] += number of 16-bit
+ * words accepted with result r, for bound <= 2^16. */
+void css_lemire16_histogram(uint32_t bound, uint64_t* counts)
+{
+    const uint32_t threshold = 0x10000u % bound;
+    for (uint32_t x = 0; x <= 0xFFFFu; ++x) {
+        uint32_t prod = x * bound;
+        if ((prod & 0xFFFFu) >= threshold) counts[prod >> 16]++;
     }
 }
 

@@ -54,7 +54,7 @@ uint32_t css_label(uint64_t seed, uint32_t stream_id, uint32_t level, uint64_t p
 
 /* Uniform draw from [0, bound) for the Fisher-Yates step at `pos`
  * (1 <= bound <= 2^32), Lemire's multiply-and-reject with the attempt
- * number in the counter. */
+ * number in the counter: 16-bit words for bounds up to 2^16, else 32-bit. */
 uint64_t css_draw(uint64_t seed, uint32_t stream_id, uint32_t level, uint64_t pos, uint64_t bound);
 
 /* One Lemire step on a given 32-bit word: returns 1 and sets *out when the
@@ -64,6 +64,9 @@ int css_lemire_step(uint32_t word, uint64_t bound, uint64_t* out);
 /* Exhaustive check helper: for every 32-bit word, run one Lemire step with
  * `bound` (<= 2^20) and add accepted results into counts[0..bound). */
 void css_lemire_histogram(uint64_t bound, uint64_t* counts);
+
+/* Exhaustive check helper for the 16-bit rule (bound <= 2^16). */
+void css_lemire16_histogram(uint32_t bound, uint64_t* counts);
 
 /* Bucket-count exponent chosen for a subproblem of m elements. */
 uint32_t css_kappa(uint64_t m, int hbm_regime, const css_params_t* p);

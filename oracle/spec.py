@@ -47,9 +47,21 @@ class PhiloxSource:
 
     def draw(self, level: int, pos: int, bound: int) -> int:
         # Lemire's multiply-and-reject (cited in Sec. 2.3); a rejected word
-        # is redrawn with the next attempt number in the counter
-        threshold = (1 << 32) % bound
+        # is redrawn with the next attempt number in the counter.  Bounds up
+        # to 2^16 take 16-bit words (eight per block, tag purpose 3), larger
+        # bounds 32-bit words (four per block, tag purpose 2).
         attempt = 0
+        if bound <= 1 << 16:
+            threshold = (1 << 16) % bound
+            while True:
+                words = self._block(pos >> 3, level | (3 << 8) | ((attempt & 0xFFFF) << 16))
+                h = pos & 7
+                x = (words[h >> 1] >> (16 * (h & 1))) & 0xFFFF
+                prod = x * bound
+                if (prod & 0xFFFF) >= threshold:
+                    return prod >> 16
+                attempt += 1
+        threshold = (1 << 32) % bound
         while True:
             words = self._block(pos >> 2, level | (2 << 8) | ((attempt & 0xFFFF) << 16))
             prod = words[pos & 3] * bound

@@ -96,6 +96,7 @@ struct LeafLayout {
     uint32_t idx;      // T u16: original leaf index of the item at each position
     uint32_t lab;      // T bytes: label bytes of the current level
     uint32_t hist;     // kWaves + 1 rows of (kmax + 1) u32 counters (last row: totals)
+                       // or a histogram of segment lengths
     uint32_t segs;     // two segment lists of seg_cap packed (start | len << 16) u32
     uint32_t tmpk;     // seg_cap + 1 u32: children per segment, then their offsets
     uint32_t misc;     // 64 u32 of scalars
@@ -115,7 +116,10 @@ __host__ __device__ __forceinline__ LeafLayout leaf_layout(uint32_t T, uint32_t 
     L.idx = 0;
     L.lab = align16(T * 2u);
     L.hist = L.lab + align16(T + 32u);  // labels of whole 16-position blocks, plus slack
-    L.segs = L.hist + align16((kWaves + 1) * (kmax + 1) * 4u);
+    // the counters also hold a 257-entry histogram of base-case segment lengths
+    uint32_t hist_words = (kWaves + 1) * (kmax + 1);
+    if (hist_words < 257u) hist_words = 257u;
+    L.segs = L.hist + align16(hist_words * 4u);
     L.tmpk = L.segs + align16(2u * seg_cap * 4u);
     L.misc = L.tmpk + align16((seg_cap + 1) * 4u);
     L.seg_cap = seg_cap;
@@ -165,12 +169,21 @@ __device__ __forceinline__ uint64_t match_label_bits(uint32_t l)
 {
     const uint64_t active = __builtin_amdgcn_read_exec();
     uint32_t lo = static_cast<uint32_t>(active), hi = static_cast<uint32_t>(active >> 32);
+    uint32_t t[KAPPA];
+    uint64_t m[KAPPA];
 #pragma unroll
     for (int i = 0; i < KAPPA; ++i) {
-        const uint32_t t = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(l), i, 1));
-        const uint64_t m = __ballot(t != 0);
-        lo = __builtin_amdgcn_bitop3_b32(lo, t, static_cast<uint32_t>(m), 0x90);
-        hi = __builtin_amdgcn_bitop3_b32(hi, t, static_cast<uint32_t>(m >> 32), 0x90);
+        t[i] = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(l), i, 1));
+        // the ballot of bit i, written as the plain compare of the extracted
+        // bit (the compiler otherwise re-derives the bit with extra shifts)
+        asm volatile("v_cmp_ne_u32_e64 %0, 0, %1" : "=s"(m[i]) : "v"(t[i]));
+    }
+    // two wait states between the last compare and the first use of its result
+    asm volatile("s_nop 1");
+#pragma unroll
+    for (int i = 0; i < KAPPA; ++i) {
+        lo = __builtin_amdgcn_bitop3_b32(lo, t[i], static_cast<uint32_t>(m[i]), 0x90);
+        hi = __builtin_amdgcn_bitop3_b32(hi, t[i], static_cast<uint32_t>(m[i] >> 32), 0x90);
     }
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }

@@ -100,7 +100,7 @@ struct HostBuf {
 struct Context {
     std::mutex mu;
     bool init = false;
-    DevBuf subs, tile_sub, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, total, ws,
+    DevBuf subs, tile_sub, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, wsp, total, ws,
         leaves, big, gfy, err, counters;
     HostBuf h_subs, h_tile_sub, h_chunk_sub, h_bk_sub, h_total, h_leaves, h_big, h_gfy, h_err,
         h_counters;
@@ -338,6 +338,7 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
         HIP_TRY(C.M.ensure(nbk * 8));
         HIP_TRY(C.K.ensure(nbk * 8));
         HIP_TRY(C.MB.ensure(nbk * 8));
+        HIP_TRY(C.wsp.ensure((nbk / kScanChunk + 2) * 8));
         HIP_TRY(grow_keep(C.leaves, (nleaves + nbk) * sizeof(LeafDesc), nleaves * sizeof(LeafDesc),
                           stream));
         HIP_TRY(C.big.ensure(nbk * sizeof(LeafDesc)));
@@ -357,6 +358,7 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
         T.M = static_cast<uint64_t*>(C.M.p);
         T.K = static_cast<uint64_t*>(C.K.p);
         T.MB = static_cast<uint64_t*>(C.MB.p);
+        T.wsp = static_cast<uint64_t*>(C.wsp.p);
         T.total = static_cast<uint64_t*>(C.total.p);
         T.err = static_cast<uint32_t*>(C.err.p);
         T.nsubs = nsub;

@@ -152,34 +152,63 @@ __global__ __launch_bounds__(kTabThreads) void k_bucket_route_scan(LevelTables T
     T.K[gb] = rk;
 }
 
-// MB = exclusive prefix of M over all buckets of the level (one workgroup)
-__global__ __launch_bounds__(1024) void k_workspace_bases(LevelTables T)
+// MB = exclusive prefix of M over all buckets of the level, in three steps:
+// per-chunk sums, a scan of the chunk sums (with the level total), and the
+// scan inside every chunk.
+__global__ __launch_bounds__(kTabThreads) void k_ws_chunk_sums(LevelTables T)
 {
-    __shared__ uint64_t part[1024];
-    const uint32_t tid = threadIdx.x;
-    const uint64_t n = T.nbuckets;
-    const uint64_t per = (n + 1023) / 1024;
-    const uint64_t b0 = tid * per;
-    const uint64_t b1 = (b0 + per) < n ? (b0 + per) : n;
+    __shared__ uint64_t part[kTabThreads];
+    const uint64_t c0 = static_cast<uint64_t>(blockIdx.x) * kScanChunk;
     uint64_t s = 0;
-    for (uint64_t i = b0; i < b1; ++i) s += T.M[i];
-    part[tid] = s;
+    for (uint64_t i = c0 + threadIdx.x; i < c0 + kScanChunk && i < T.nbuckets; i += kTabThreads)
+        s += T.M[i];
+    part[threadIdx.x] = s;
     __syncthreads();
-    if (tid == 0) {
-        uint64_t run = 0;
-        for (int i = 0; i < 1024; ++i) {
+    for (uint32_t d = kTabThreads / 2; d > 0; d >>= 1) {
+        if (threadIdx.x < d) part[threadIdx.x] += part[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) T.wsp[blockIdx.x] = part[0];
+}
+
+__global__ void k_ws_scan_sums(LevelTables T, uint32_t nparts)
+{
+    if (threadIdx.x != 0) return;
+    uint64_t run = 0;
+    for (uint32_t i = 0; i < nparts; ++i) {
+        const uint64_t v = T.wsp[i];
+        T.wsp[i] = run;
+        run += v;
+    }
+    *T.total = run;
+}
+
+__global__ __launch_bounds__(kTabThreads) void k_ws_chunk_scan(LevelTables T)
+{
+    constexpr uint32_t per = kScanChunk / kTabThreads;  // consecutive buckets per thread
+    __shared__ uint64_t part[kTabThreads];
+    const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * kScanChunk + threadIdx.x * per;
+    uint64_t s = 0;
+    for (uint32_t j = 0; j < per; ++j)
+        if (b0 + j < T.nbuckets) s += T.M[b0 + j];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t run = T.wsp[blockIdx.x];
+        for (uint32_t i = 0; i < kTabThreads; ++i) {
             const uint64_t v = part[i];
             part[i] = run;
             run += v;
         }
-        *T.total = run;
     }
     __syncthreads();
-    uint64_t run = part[tid];
-    for (uint64_t i = b0; i < b1; ++i) {
-        const uint64_t v = T.M[i];
-        T.MB[i] = run;
-        run += v;
+    uint64_t run = part[threadIdx.x];
+    for (uint32_t j = 0; j < per; ++j) {
+        if (b0 + j < T.nbuckets) {
+            const uint64_t v = T.M[b0 + j];
+            T.MB[b0 + j] = run;
+            run += v;
+        }
     }
 }
 
@@ -364,7 +393,10 @@ hipError_t launch_tables_routes(const LevelTables& t, hipStream_t stream)
     hipLaunchKernelGGL(k_bucket_route_scan,
                        dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads - 1) / kTabThreads)),
                        dim3(kTabThreads), 0, stream, t);
-    hipLaunchKernelGGL(k_workspace_bases, dim3(1), dim3(1024), 0, stream, t);
+    const uint32_t nparts = static_cast<uint32_t>((t.nbuckets + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(k_ws_chunk_sums, dim3(nparts), dim3(kTabThreads), 0, stream, t);
+    hipLaunchKernelGGL(k_ws_scan_sums, dim3(1), dim3(64), 0, stream, t, nparts);
+    hipLaunchKernelGGL(k_ws_chunk_scan, dim3(nparts), dim3(kTabThreads), 0, stream, t);
     hipLaunchKernelGGL(k_chunk_route_prefix, dim3(static_cast<uint32_t>(t.nchunks)),
                        dim3(kTabThreads), 0, stream, t);
     return hipGetLastError();

@@ -42,29 +42,35 @@ __device__ __forceinline__ uint32_t kappa_in_tile(uint32_t m, const Params& prm)
     return kap < prm.kmax_log2 ? kap : prm.kmax_log2;
 }
 
-// Fisher-Yates on idx[s0, s0 + len) (len >= 2): i from len-1 down to 1, the
-// partner drawn from [0, i] at position pbase + s0 + i.  One Philox block
-// serves the four positions 4B..4B+3.  The lanes of a wave run different
-// segments, so each lane starts after o idle steps, o chosen so that every
-// lane enters a new block on the same step: the block is then computed once
-// per four steps for the whole wave.
+// Fisher-Yates on idx[s0, s0 + len) (2 <= len <= 2^16): i from len-1 down
+// to 1, the partner drawn from [0, i] at position pbase + s0 + i with a short
+// draw.  One Philox block serves the eight positions 8B..8B+7.  The lanes of
+// a wave run different segments, so each lane starts after o idle steps, o
+// chosen so that every lane enters a new block on the same step: the block
+// is then computed once per eight steps for the whole wave, and the 16-bit
+// word a step uses is known at compile time.
 __device__ void fy_segment(uint16_t* idx, uint32_t s0, uint32_t len, uint64_t pbase,
                            uint32_t level, const Key& key)
 {
-    const uint64_t top = pbase + s0 + len - 1;           // position of the first step
-    const uint32_t o = (3u - static_cast<uint32_t>(top & 3)) & 3u;
+    const uint64_t top = pbase + s0 + len - 1;  // position of the first step
+    const uint32_t o = (7u - static_cast<uint32_t>(top & 7)) & 7u;
     const uint32_t steps = o + len - 1;
-    Word4 v = {0, 0, 0, 0};
-    for (uint32_t s = 0; s < steps; ++s) {
-        // virtual position top + o - s; a block starts every four steps
-        const uint64_t vp = top + o - s;
-        if ((s & 3) == 0) v = fy_block(key, level, vp >> 2, 0);
-        if (s < o) continue;
-        const uint32_t i = len - 1 - (s - o);
-        const uint32_t j = fy_draw_from(key, level, vp, i + 1, v);
-        const uint16_t a = idx[s0 + i];
-        idx[s0 + i] = idx[s0 + j];
-        idx[s0 + j] = a;
+    for (uint32_t s8 = 0; s8 < steps; s8 += 8) {
+        // virtual position of step s is top + o - s; (top + o) mod 8 = 7
+        const uint64_t vb = (top + o - s8) >> 3;
+        const Word4 v = fy_short_block(key, level, vb, 0);
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) {
+            const uint32_t s = s8 + u;
+            if (s >= o && s < steps) {
+                const uint32_t i = len - 1 - (s - o);
+                const uint32_t x = half_of(v, 7 - u);
+                const uint32_t j = fy_short_draw(key, level, top + o - s, i + 1, x);
+                const uint16_t a = idx[s0 + i];
+                idx[s0 + i] = idx[s0 + j];
+                idx[s0 + j] = a;
+            }
+        }
     }
 }
 
@@ -193,9 +199,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
     // labraw holds whole label blocks; lab[x] is the label byte of position pbase + x
     const uint8_t* lab = labraw + (pbase & 15);
 
+    const uint32_t mr = (m + kThreads - 1) / kThreads;  // rounds of kThreads items
     E data[EMAX];
 #pragma unroll
     for (int r = 0; r < EMAX; ++r) {
+        if (static_cast<uint32_t>(r) >= mr) break;
         const uint32_t q = r * kThreads + tid;
         if (q < m) data[r] = X[q];
     }
@@ -214,24 +222,40 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
         if (tid == 0) misc[1] = 0;
         __syncthreads();
 
-        // Classify the segments; base-case segments run Fisher-Yates now.
-        // Segment i goes to lane (i / kWaves) % 64 of wave i % kWaves, so that
-        // the sequential Fisher-Yates work is spread over all waves.
-        for (uint32_t base = 0; base < nseg; base += kThreads) {
-            const uint32_t i = base + lane * kWaves + wv;
-            if (i >= nseg) continue;
+        // Classify the segments.  Base-case segments are listed longest first
+        // (counting sort on the length, kept in the next-level list, which is
+        // only written by the splits below) so that the lanes of one wave run
+        // Fisher-Yates on segments of similar length.
+        for (uint32_t j = tid; j < 257; j += kThreads) H[j] = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < nseg; i += kThreads) {
             const uint32_t e = cur[i];
-            const uint32_t s0 = seg_start(e), len = seg_len(e);
+            const uint32_t len = seg_len(e);
             uint32_t kk = 0;
             if (len >= 2) {
                 if (len <= prm.n0 || level >= prm.lmax) {
-                    fy_segment(idx, s0, len, pbase, level, key);
+                    atomicAdd(&H[255 - (len < 255 ? len : 255)], 1u);
                 } else {
                     kk = 1u << kappa_in_tile(len, prm);
                     if (len > kWaveSegMax) misc[2 + atomicAdd(&misc[1], 1u)] = i;
                 }
             }
             tmpk[i] = kk;
+        }
+        __syncthreads();
+        if (wv == 0) wave_exclusive_scan(H, 256);
+        __syncthreads();
+        const uint32_t nfy = H[256];
+        for (uint32_t i = tid; i < nseg; i += kThreads) {
+            const uint32_t e = cur[i];
+            const uint32_t len = seg_len(e);
+            if (len >= 2 && (len <= prm.n0 || level >= prm.lmax))
+                nxt[atomicAdd(&H[255 - (len < 255 ? len : 255)], 1u)] = e;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < nfy; i += kThreads) {
+            const uint32_t e = nxt[i];
+            fy_segment(idx, seg_start(e), seg_len(e), pbase, level, key);
         }
         // Label bytes of this level: whole 16-byte blocks, aligned.
         {
@@ -296,12 +320,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
     uint32_t v[kRounds];
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
+        if (r >= mr) break;
         const uint32_t x = r * kThreads + tid;
         if (x < m) v[r] = idx[x];
     }
     __syncthreads();
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
+        if (r >= mr) break;
         const uint32_t x = r * kThreads + tid;
         if (x < m) idx[v[r]] = static_cast<uint16_t>(x);
     }
@@ -309,12 +335,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
     uint32_t dst[EMAX];
 #pragma unroll
     for (int r = 0; r < EMAX; ++r) {
+        if (static_cast<uint32_t>(r) >= mr) break;
         const uint32_t q = r * kThreads + tid;
         if (q < m) dst[r] = idx[q];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < EMAX; ++r) {
+        if (static_cast<uint32_t>(r) >= mr) break;
         const uint32_t q = r * kThreads + tid;
         if (q < m) stage[dst[r]] = data[r];
     }
@@ -332,8 +360,14 @@ __global__ void k_fy_global(uint8_t* __restrict__ buf, const LeafDesc* __restric
     const Key key = make_key(seed, ld.stream_id);
     for (uint64_t i = ld.m - 1; i >= 1; --i) {
         const uint64_t p = ld.base + i;
-        const Word4 v = fy_block(key, ld.level, p >> 2, 0);
-        const uint64_t j = fy_draw_from(key, ld.level, p, static_cast<uint32_t>(i + 1), v);
+        const uint32_t bound = static_cast<uint32_t>(i + 1);
+        uint64_t j;
+        if (bound <= 0x10000u) {
+            const Word4 v = fy_short_block(key, ld.level, p >> 3, 0);
+            j = fy_short_draw(key, ld.level, p, bound, half_of(v, static_cast<uint32_t>(p & 7)));
+        } else {
+            j = fy_long_draw(key, ld.level, p, bound);
+        }
         const E a = X[i];
         X[i] = X[j];
         X[j] = a;

@@ -35,10 +35,13 @@ struct LevelTables {
     uint64_t* K;                // [bucket] kept items
     uint64_t* MB;               // [bucket] workspace start of the bucket's movers
     uint64_t* total;            // [1] workspace elements of the level
+    uint64_t* wsp;              // [nbuckets / kScanChunk + 1] partial sums of the workspace scan
     uint32_t* err;              // [1] set non-zero by a kernel that finds an index out of range
     uint64_t ws_cap;            // workspace elements available to gather / scatter
     uint64_t nsubs, ntiles, nchunks, nbuckets;
 };
+
+constexpr uint32_t kScanChunk = 4096;  // buckets per block of the workspace scan
 
 // Children of a tiled level: those that fit a tile are appended to the leaf
 // list (leaves[counters[0]++], counters[2] += elements), larger ones to the

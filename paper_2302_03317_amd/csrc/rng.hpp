@@ -68,14 +68,51 @@ __device__ __forceinline__ uint32_t block_byte(const Word4& v, uint32_t j)
     return (word_of(v, j >> 2) >> (8 * (j & 3))) & 0xFFu;
 }
 
-// Lemire's multiply-and-reject: word x is accepted for bound s when the low
-// half of x*s is at least 2^32 mod s; the high half is the draw.  The 32-bit
-// word of position p is word (p mod 4) of block p / 4; a rejected word is
-// replaced by the same word of the block with the next attempt number.  As
-// 2^32 mod s < s, a low half of at least s is accepted without computing the
-// threshold.  The attempt loop stops after 2^16 attempts so that it always
-// terminates (2^16 rejections in a row have probability below 2^-65536).
-// `first` is the attempt-0 block of position `pos`.
+// Fisher-Yates draws, Lemire's multiply-and-reject: a word x is accepted for
+// bound s when the low half of x*s is at least (word range) mod s, and the
+// high half is the draw; a rejected word is replaced by the same word of the
+// block with the next attempt number.
+//  - bounds up to 2^16 ("short"): 16-bit words, eight per Philox block
+//    (position p uses half (p mod 2) -- low half first -- of word (p mod 8)/2
+//    of block p / 8), tag purpose 3;
+//  - larger bounds ("long"): 32-bit words, word p mod 4 of block p / 4, tag
+//    purpose 2.
+// Since (range mod s) < s, a low half of at least s is accepted without
+// computing the threshold.  The attempt loops stop after 2^16 attempts so
+// that they always terminate (2^16 rejections in a row have probability
+// below 2^-65536).
+constexpr uint32_t kPurposeFYShort = 3u;
+
+__device__ __forceinline__ Word4 fy_short_block(const Key& key, uint32_t level, uint64_t block,
+                                                uint32_t attempt)
+{
+    return philox10(static_cast<uint32_t>(block), static_cast<uint32_t>(block >> 32),
+                    level | (kPurposeFYShort << 8) | (attempt << 16), key.stream, key.k0, key.k1);
+}
+
+// 16-bit word h (0..7) of a block.
+__device__ __forceinline__ uint32_t half_of(const Word4& v, uint32_t h)
+{
+    return (word_of(v, h >> 1) >> (16 * (h & 1))) & 0xFFFFu;
+}
+
+// Short draw for position `pos` with bound <= 2^16, given its attempt-0 word.
+__device__ __forceinline__ uint32_t fy_short_draw(const Key& key, uint32_t level, uint64_t pos,
+                                                  uint32_t bound, uint32_t first_word)
+{
+    uint32_t prod = first_word * bound;
+    if ((prod & 0xFFFFu) < bound) {
+        const uint32_t threshold = 0x10000u % bound;
+        uint32_t attempt = 0;
+        while ((prod & 0xFFFFu) < threshold && attempt < 65535u) {
+            ++attempt;
+            const Word4 v = fy_short_block(key, level, pos >> 3, attempt);
+            prod = half_of(v, static_cast<uint32_t>(pos & 7)) * bound;
+        }
+    }
+    return prod >> 16;
+}
+
 __device__ __forceinline__ Word4 fy_block(const Key& key, uint32_t level, uint64_t block,
                                           uint32_t attempt)
 {
@@ -83,19 +120,17 @@ __device__ __forceinline__ Word4 fy_block(const Key& key, uint32_t level, uint64
                     level | (kPurposeFY << 8) | (attempt << 16), key.stream, key.k0, key.k1);
 }
 
-__device__ __forceinline__ uint32_t fy_draw_from(const Key& key, uint32_t level, uint64_t pos,
-                                                 uint32_t bound, const Word4& first)
+// Long draw for position `pos` with bound in (2^16, 2^32).
+__device__ __forceinline__ uint32_t fy_long_draw(const Key& key, uint32_t level, uint64_t pos,
+                                                 uint32_t bound)
 {
     const uint32_t j = static_cast<uint32_t>(pos & 3);
-    uint64_t prod = static_cast<uint64_t>(word_of(first, j)) * bound;
-    if (static_cast<uint32_t>(prod) < bound) {
-        const uint32_t threshold = (0u - bound) % bound;  // 2^32 mod bound
-        uint32_t attempt = 0;
-        while (static_cast<uint32_t>(prod) < threshold && attempt < 65535u) {
-            ++attempt;
-            const Word4 v = fy_block(key, level, pos >> 2, attempt);
-            prod = static_cast<uint64_t>(word_of(v, j)) * bound;
-        }
+    const uint32_t threshold = (0u - bound) % bound;  // 2^32 mod bound
+    uint64_t prod = 0;
+    for (uint32_t attempt = 0; attempt < 65536u; ++attempt) {
+        const Word4 v = fy_block(key, level, pos >> 2, attempt);
+        prod = static_cast<uint64_t>(word_of(v, j)) * bound;
+        if (static_cast<uint32_t>(prod) >= threshold) break;
     }
     return static_cast<uint32_t>(prod >> 32);
 }

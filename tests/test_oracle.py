@@ -101,6 +101,14 @@ def test_lemire_exhaustive_counts():
     assert np.all(h == (1 << 32) // s)
 
 
+def test_lemire16_exhaustive_counts():
+    """16-bit rule: for every bound up to 2^16 tried, every result in [0, s)
+    is accepted for exactly floor(2^16 / s) of the 2^16 words."""
+    for s in [1, 2, 3, 5, 6, 7, 10, 21, 63, 64, 100, 1000, 4097, 32768, 40000, 65535, 65536]:
+        h = oracle.lemire16_histogram(s)
+        assert np.all(h == (1 << 16) // s), s
+
+
 def test_lemire_threshold_closed_form():
     rng = random.Random(3)
     for s in [1, 2, 3, 7, 1000, 65537, (1 << 31) + 1, (1 << 32) - 1, 1 << 32]:
@@ -118,12 +126,29 @@ def test_draw_in_range_and_retry_counter():
     for s in [2, 3, 5, 64, 1000]:
         for pos in range(200):
             assert 0 <= oracle.draw(5, 1, 2, pos, s) < s
-    # a bound of 2^32 - 1 rejects only word 0xFFFFFFFF... with threshold 1
-    # the draw must equal the spec's attempt-by-attempt rendition
+    # the draw must equal the spec's attempt-by-attempt rendition, on both
+    # sides of the 16-bit / 32-bit switch and for bounds with many rejections
     src = spec.PhiloxSource(77, 4)
     for pos in range(300):
-        for s in [3, (1 << 31) + 1, (1 << 32) - 1]:
+        for s in [3, 40000, 65535, 65536, 65537, (1 << 31) + 1, (1 << 32) - 1]:
             assert oracle.draw(77, 4, 9, pos, s) == src.draw(9, pos, s)
+
+
+def test_draw_word_layout():
+    """Short draws read 16-bit half-words of block pos >> 3, low half first;
+    long draws read 32-bit words of block pos >> 2."""
+    seed, stream, level = 1234567, 3, 5
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for pos in [0, 1, 7, 8, 13, 1 << 35]:
+        words = oracle.philox4x32_10([(pos >> 3) & 0xFFFFFFFF, pos >> 35, level | (3 << 8), stream], key)
+        x = (words[(pos & 7) >> 1] >> (16 * (pos & 1))) & 0xFFFF
+        for s in [2, 6, 64]:
+            if ((x * s) & 0xFFFF) >= (1 << 16) % s:
+                assert oracle.draw(seed, stream, level, pos, s) == (x * s) >> 16
+        words = oracle.philox4x32_10([(pos >> 2) & 0xFFFFFFFF, pos >> 34, level | (2 << 8), stream], key)
+        s = (1 << 20) + 3
+        if ((words[pos & 3] * s) & 0xFFFFFFFF) >= (1 << 32) % s:
+            assert oracle.draw(seed, stream, level, pos, s) == (words[pos & 3] * s) >> 32
 
 
 # ------------------------------------------------------------ kappa rule ---
