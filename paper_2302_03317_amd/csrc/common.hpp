@@ -99,6 +99,7 @@ struct LeafLayout {
                        // or a histogram of segment lengths
     uint32_t segs;     // two segment lists of seg_cap packed (start | len << 16) u32
     uint32_t tmpk;     // seg_cap + 1 u32: children per segment, then their offsets
+    uint32_t wl;       // seg_cap u32: segments split by one wave
     uint32_t misc;     // 64 u32 of scalars
     uint32_t seg_cap;  // entries of one segment list
     uint32_t total;    // bytes, the final staging copy of the elements overlays all
@@ -121,7 +122,8 @@ __host__ __device__ __forceinline__ LeafLayout leaf_layout(uint32_t T, uint32_t 
     if (hist_words < 257u) hist_words = 257u;
     L.segs = L.hist + align16(hist_words * 4u);
     L.tmpk = L.segs + align16(2u * seg_cap * 4u);
-    L.misc = L.tmpk + align16((seg_cap + 1) * 4u);
+    L.wl = L.tmpk + align16((seg_cap + 1) * 4u);
+    L.misc = L.wl + align16(seg_cap * 4u);
     L.seg_cap = seg_cap;
     const uint32_t work = L.misc + 64u * 4u;
     const uint32_t stage = align16(T * w);
@@ -139,24 +141,19 @@ __device__ __forceinline__ uint32_t bits_below(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave.
+// Inclusive prefix sum across the 64 lanes of a wave, with all 64 lanes
+// active.  Data-parallel-primitive moves: a shift by 1, 2, 4, 8 lanes inside
+// each row of 16 (lanes shifted in from outside the row contribute 0), then
+// lane 15 of rows 0 and 2 added to rows 1 and 3, and lane 31 added to rows 2
+// and 3.  Lanes a move does not write keep the initial 0.
 __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(v, d, 64);
-        if (static_cast<int>(lane_id()) >= d) v += o;
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint64_t wave_inclusive_sum64(uint64_t v)
-{
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t o = __shfl_up(v, d, 64);
-        if (static_cast<int>(lane_id()) >= d) v += o;
-    }
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xF, 0xF, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xF, 0xF, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xF, 0xF, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xF, 0xF, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xA, 0xF, false));
+    v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xC, 0xF, false));
     return v;
 }
 
@@ -211,7 +208,7 @@ __device__ __forceinline__ void wave_exclusive_scan(uint32_t* a, uint32_t n)
             if (j < n) a[j] = run;
             run += v[i];
         }
-        carry += __shfl(incl, 63, 64);
+        carry += static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(incl), 63));
     }
     if (lane == 0) a[n] = carry;
 }

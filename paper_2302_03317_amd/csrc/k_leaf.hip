@@ -2,15 +2,14 @@
 // levels of ScatterShuffle (arXiv 2302.03317, Sec. 3.1 / Fig. 2) and the
 // Fisher-Yates base case (Fig. 1).
 //
-// One workgroup per subproblem ("leaf").  The elements are loaded once into
-// registers at the start (the loads overlap all index work) and written once
-// at the end.  In between only 16-bit indices move: idx[x] is the original
+// One workgroup per subproblem ("leaf").  Only 16-bit indices move while the
+// levels run: idx[x] is the original
 // leaf index of the item at position x.  Each in-tile level is a stable
 // counting sort of every splitting segment by its label; segments larger
 // than one wave can hold are split by the whole workgroup, the others by one
 // wave each.  Segments at the base case run Fisher-Yates, one lane per
-// segment.  Finally every item's destination is read off the index array and
-// the elements go through an LDS staging copy to HBM.
+// segment.  Finally the elements are read once from HBM into an LDS staging
+// copy and written once, every position gathering its item by the index array.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "rng.hpp"
@@ -49,8 +48,8 @@ __device__ __forceinline__ uint32_t kappa_in_tile(uint32_t m, const Params& prm)
 // chosen so that every lane enters a new block on the same step: the block
 // is then computed once per eight steps for the whole wave, and the 16-bit
 // word a step uses is known at compile time.
-__device__ void fy_segment(uint16_t* idx, uint32_t s0, uint32_t len, uint64_t pbase,
-                           uint32_t level, const Key& key)
+__device__ __forceinline__ void fy_segment(uint16_t* idx, uint32_t s0, uint32_t len, uint64_t pbase,
+                                           uint32_t level, const Key& key)
 {
     const uint64_t top = pbase + s0 + len - 1;  // position of the first step
     const uint32_t o = (7u - static_cast<uint32_t>(top & 7)) & 7u;
@@ -93,10 +92,9 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
     uint32_t pk[kRounds];
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
-        if (r >= rounds) break;
         const uint32_t x = first + 64u * r;
         uint32_t v = 0;
-        if (x < end) {
+        if (r < rounds && x < end) {
             const uint32_t l = lab[x] >> sh;
             const uint64_t peers = match_label_bits<KAPPA>(l);
             const uint32_t below = bits_below(peers);
@@ -123,9 +121,8 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
         out[l] = seg_pack(s0 + Htot[l], Htot[l + 1] - Htot[l]);
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
-        if (r >= rounds) break;
         const uint32_t x = first + 64u * r;
-        if (x < end) {
+        if (r < rounds && x < end) {
             const uint32_t l = lab[x] >> sh;
             idx[s0 + Htot[l] + H[wv * hs + l] + (pk[r] >> 16)] = static_cast<uint16_t>(pk[r]);
         }
@@ -146,10 +143,9 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
     uint32_t pk[kRounds];
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
-        if (r >= rounds) break;
         const uint32_t x = s0 + 64u * r + lane;
         uint32_t v = 0;
-        if (x < end) {
+        if (r < rounds && x < end) {
             const uint32_t l = lab[x] >> sh;
             const uint64_t peers = match_label_bits<KAPPA>(l);
             const uint32_t below = bits_below(peers);
@@ -163,9 +159,8 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
     for (uint32_t l = lane; l < k; l += 64) out[l] = seg_pack(s0 + Hw[l], Hw[l + 1] - Hw[l]);
 #pragma unroll
     for (uint32_t r = 0; r < kRounds; ++r) {
-        if (r >= rounds) break;
         const uint32_t x = s0 + 64u * r + lane;
-        if (x < end) {
+        if (r < rounds && x < end) {
             const uint32_t l = lab[x] >> sh;
             idx[s0 + Hw[l] + (pk[r] >> 16)] = static_cast<uint16_t>(pk[r]);
         }
@@ -190,7 +185,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
     uint32_t* cur = reinterpret_cast<uint32_t*>(smem + LL.segs);
     uint32_t* nxt = cur + LL.seg_cap;
     uint32_t* tmpk = reinterpret_cast<uint32_t*>(smem + LL.tmpk);
-    uint32_t* misc = reinterpret_cast<uint32_t*>(smem + LL.misc);  // [0] segments, [1] big, [2..) big list
+    uint32_t* wl = reinterpret_cast<uint32_t*>(smem + LL.wl);
+    // misc: [0] segments of the level, [1] large splitting segments,
+    // [2] segments split by one wave, [3] base-case segments, [4..) large list
+    uint32_t* misc = reinterpret_cast<uint32_t*>(smem + LL.misc);
     E* stage = reinterpret_cast<E*>(smem);
 
     E* X = reinterpret_cast<E*>(buf) + ld.elem_off + ld.base;
@@ -199,64 +197,73 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
     // labraw holds whole label blocks; lab[x] is the label byte of position pbase + x
     const uint8_t* lab = labraw + (pbase & 15);
 
-    const uint32_t mr = (m + kThreads - 1) / kThreads;  // rounds of kThreads items
-    E data[EMAX];
-#pragma unroll
-    for (int r = 0; r < EMAX; ++r) {
-        if (static_cast<uint32_t>(r) >= mr) break;
-        const uint32_t q = r * kThreads + tid;
-        if (q < m) data[r] = X[q];
-    }
     for (uint32_t x = tid; x < m; x += kThreads) idx[x] = static_cast<uint16_t>(x);
-    if (tid == 0) {
-        cur[0] = seg_pack(0, m);
-        misc[0] = 1;
-    }
-    __syncthreads();
 
+    // The first level has the single segment [0, m), classified right here.
     uint32_t level = ld.level;
+    if (tid == 0) {
+        const bool base = m <= prm.n0 || level >= prm.lmax;
+        const bool split = m >= 2 && !base;
+        cur[0] = seg_pack(0, m);
+        nxt[0] = cur[0];
+        tmpk[0] = split ? (1u << kappa_in_tile(m, prm)) : 0u;
+        wl[0] = 0;
+        misc[0] = 1;
+        misc[1] = (split && m > kWaveSegMax) ? 1u : 0u;
+        misc[2] = (split && m <= kWaveSegMax) ? 1u : 0u;
+        misc[3] = (m >= 2 && base) ? 1u : 0u;
+        misc[4] = 0;
+    }
+    bool classified = true;
     for (;;) {
+        __syncthreads();
         const uint32_t nseg = misc[0];
         if (nseg == 0) break;
-        __syncthreads();
-        if (tid == 0) misc[1] = 0;
-        __syncthreads();
-
-        // Classify the segments.  Base-case segments are listed longest first
-        // (counting sort on the length, kept in the next-level list, which is
-        // only written by the splits below) so that the lanes of one wave run
-        // Fisher-Yates on segments of similar length.
-        for (uint32_t j = tid; j < 257; j += kThreads) H[j] = 0;
-        __syncthreads();
-        for (uint32_t i = tid; i < nseg; i += kThreads) {
-            const uint32_t e = cur[i];
-            const uint32_t len = seg_len(e);
-            uint32_t kk = 0;
-            if (len >= 2) {
-                if (len <= prm.n0 || level >= prm.lmax) {
-                    atomicAdd(&H[255 - (len < 255 ? len : 255)], 1u);
-                } else {
-                    kk = 1u << kappa_in_tile(len, prm);
-                    if (len > kWaveSegMax) misc[2 + atomicAdd(&misc[1], 1u)] = i;
-                }
+        if (!classified) {
+            // Base-case segments are listed longest first (counting sort on
+            // the length, kept in the next-level list, which only the splits
+            // below write) so that the lanes of one wave run Fisher-Yates on
+            // segments of similar length.  Splitting segments go to the large
+            // list or to the one-wave list.
+            for (uint32_t j = tid; j < 257; j += kThreads) H[j] = 0;
+            if (tid == 0) {
+                misc[1] = 0;
+                misc[2] = 0;
             }
-            tmpk[i] = kk;
+            __syncthreads();
+            for (uint32_t i = tid; i < nseg; i += kThreads) {
+                const uint32_t len = seg_len(cur[i]);
+                uint32_t kk = 0;
+                if (len >= 2) {
+                    if (len <= prm.n0 || level >= prm.lmax) {
+                        atomicAdd(&H[255 - (len < 255 ? len : 255)], 1u);
+                    } else {
+                        kk = 1u << kappa_in_tile(len, prm);
+                        if (len > kWaveSegMax) misc[4 + atomicAdd(&misc[1], 1u)] = i;
+                        else wl[atomicAdd(&misc[2], 1u)] = i;
+                    }
+                }
+                tmpk[i] = kk;
+            }
+            __syncthreads();
+            if (wv == 0) wave_exclusive_scan(H, 256);
+            __syncthreads();
+            for (uint32_t i = tid; i < nseg; i += kThreads) {
+                const uint32_t e = cur[i];
+                const uint32_t len = seg_len(e);
+                if (len >= 2 && (len <= prm.n0 || level >= prm.lmax))
+                    nxt[atomicAdd(&H[255 - (len < 255 ? len : 255)], 1u)] = e;
+            }
+            if (tid == 0) misc[3] = H[256];
+            __syncthreads();
         }
-        __syncthreads();
-        if (wv == 0) wave_exclusive_scan(H, 256);
-        __syncthreads();
-        const uint32_t nfy = H[256];
-        for (uint32_t i = tid; i < nseg; i += kThreads) {
-            const uint32_t e = cur[i];
-            const uint32_t len = seg_len(e);
-            if (len >= 2 && (len <= prm.n0 || level >= prm.lmax))
-                nxt[atomicAdd(&H[255 - (len < 255 ? len : 255)], 1u)] = e;
-        }
-        __syncthreads();
+        classified = false;
+        const uint32_t nbig = misc[1], nwave = misc[2], nfy = misc[3];
         for (uint32_t i = tid; i < nfy; i += kThreads) {
             const uint32_t e = nxt[i];
             fy_segment(idx, seg_start(e), seg_len(e), pbase, level, key);
         }
+        if (nbig + nwave == 0) break;
         // Label bytes of this level: whole 16-byte blocks, aligned.
         {
             const uint64_t b0 = pbase >> 4;
@@ -269,11 +276,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
         __syncthreads();
         if (wv == 0) wave_exclusive_scan(tmpk, nseg);  // child offsets; tmpk[nseg] = total
         __syncthreads();
-        const uint32_t nbig = misc[1];
 
         // Large segments: the whole workgroup, one segment at a time.
         for (uint32_t bi = 0; bi < nbig; ++bi) {
-            const uint32_t i = misc[2 + bi];
+            const uint32_t i = misc[4 + bi];
             const uint32_t e = cur[i];
             const uint32_t s0 = seg_start(e), len = seg_len(e);
             uint32_t* out = nxt + tmpk[i];
@@ -290,10 +296,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
         }
 
         // Other splitting segments: one wave each.
-        for (uint32_t i = wv; i < nseg; i += kWaves) {
+        for (uint32_t j = wv; j < nwave; j += kWaves) {
+            const uint32_t i = wl[j];
             const uint32_t e = cur[i];
             const uint32_t s0 = seg_start(e), len = seg_len(e);
-            if (len < 2 || len <= prm.n0 || level >= prm.lmax || len > kWaveSegMax) continue;
             uint32_t* Hw = H + wv * hs;
             uint32_t* out = nxt + tmpk[i];
             switch (kappa_in_tile(len, prm)) {
@@ -313,41 +319,34 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
         cur = nxt;
         nxt = sw;
         ++level;
-        __syncthreads();
     }
+    __syncthreads();
 
-    // idx[x] = original index of the item ending at x; invert it in place.
-    uint32_t v[kRounds];
-#pragma unroll
-    for (uint32_t r = 0; r < kRounds; ++r) {
-        if (r >= mr) break;
-        const uint32_t x = r * kThreads + tid;
-        if (x < m) v[r] = idx[x];
-    }
-    __syncthreads();
-#pragma unroll
-    for (uint32_t r = 0; r < kRounds; ++r) {
-        if (r >= mr) break;
-        const uint32_t x = r * kThreads + tid;
-        if (x < m) idx[v[r]] = static_cast<uint16_t>(x);
-    }
-    __syncthreads();
-    uint32_t dst[EMAX];
+    // idx[x] is the leaf index of the item that ends at x.  The elements come
+    // from HBM straight into the staging copy (over the dead index arrays),
+    // and every position gathers its item from there.
+    uint32_t src[EMAX];
 #pragma unroll
     for (int r = 0; r < EMAX; ++r) {
-        if (static_cast<uint32_t>(r) >= mr) break;
-        const uint32_t q = r * kThreads + tid;
-        if (q < m) dst[r] = idx[q];
+        const uint32_t x = r * kThreads + tid;
+        if (x < m) src[r] = idx[x];
+    }
+    __syncthreads();
+    {
+        const uint32_t nw = m * static_cast<uint32_t>(sizeof(E) / 4);
+        const uint32_t* from = reinterpret_cast<const uint32_t*>(X);
+        uint32_t* to = reinterpret_cast<uint32_t*>(stage);
+        for (uint32_t j = wv * 64u; j < nw; j += kThreads) {
+            if (j + lane < nw) __builtin_amdgcn_global_load_lds(from + j + lane, to + j, 4, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < EMAX; ++r) {
-        if (static_cast<uint32_t>(r) >= mr) break;
-        const uint32_t q = r * kThreads + tid;
-        if (q < m) stage[dst[r]] = data[r];
+        const uint32_t x = r * kThreads + tid;
+        if (x < m) X[x] = stage[src[r]];
     }
-    __syncthreads();
-    for (uint32_t x = tid; x < m; x += kThreads) X[x] = stage[x];
 }
 
 template <typename E>
