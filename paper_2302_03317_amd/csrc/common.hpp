@@ -77,19 +77,28 @@ __host__ __device__ __forceinline__ Piece piece_of(uint64_t m, uint32_t kappa, u
 __host__ __device__ __forceinline__ uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 
 struct RoughLayout {
-    uint32_t stage;    // T elements of staging (labels and per-wave counts overlay it)
+    uint32_t stage;    // T elements of staging; labels, counters and slot tables overlay it
+    uint32_t counts;   // per-wave counters: kWaves rows of (kmax + 1) u32
+    uint32_t slot_tab; // per-wave slot table: kWaves rows of kmax uint2
     uint32_t tables;   // offset of the per-piece tables
+    uint32_t bpiece;   // piece of every label block, one byte each
     uint32_t total;
 };
 
 __host__ __device__ __forceinline__ RoughLayout rough_layout(uint32_t T, uint32_t w, uint32_t kmax)
 {
-    const uint32_t overlay = align16(T) + kWaves * (kmax + 1) * 4u;
-    uint32_t stage = align16(T * w);
-    if (overlay > stage) stage = align16(overlay);
+    RoughLayout L;
+    L.counts = align16(T);
+    L.slot_tab = L.counts + align16(kWaves * (kmax + 1) * 4u);
+    const uint32_t overlay = L.slot_tab + kWaves * kmax * 8u;
+    L.stage = align16(T * w);
+    if (overlay > L.stage) L.stage = align16(overlay);
     // lo: (kmax+1) u64; qoff, cap, fill, ovt, hot, nblk: (kmax+1) u32 each; 16 u32 misc
-    const uint32_t tables = (kmax + 1) * 8u + 6u * (kmax + 1) * 4u + 64u;
-    return {stage, stage, stage + align16(tables)};
+    L.tables = L.stage;
+    L.bpiece = L.tables + align16((kmax + 1) * 8u + 6u * (kmax + 1) * 4u + 64u);
+    // a piece of c items touches at most c/16 + 2 label blocks
+    L.total = L.bpiece + align16(T / 16u + 2u * kmax + 16u);
+    return L;
 }
 
 struct LeafLayout {

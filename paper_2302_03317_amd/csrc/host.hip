@@ -101,7 +101,7 @@ struct Context {
     std::mutex mu;
     bool init = false;
     DevBuf subs, tile_sub, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, wsp, total, ws,
-        leaves, big, gfy, err, counters;
+        leaves, leaves_cls, big, gfy, err, counters;
     HostBuf h_subs, h_tile_sub, h_chunk_sub, h_bk_sub, h_total, h_leaves, h_big, h_gfy, h_err,
         h_counters;
     shuf_stats_t stats{};
@@ -420,8 +420,20 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
         if (f.m > 0xFFFFFFFFull) return SHUF_EUNSUPPORTED;
     if (nleaves) {
         SpanGuard g(C, stream, 4, 2.0 * static_cast<double>(leaf_elems) * w);
-        HIP_TRY(launch_leaf(w, buf, static_cast<const LeafDesc*>(C.leaves.p), nleaves, seed, prm,
-                            stream));
+        uint32_t caps[3];
+        leaf_class_caps(w, prm, caps);
+        HIP_TRY(C.leaves_cls.ensure(3 * nleaves * sizeof(LeafDesc)));
+        unsigned long long* dc = static_cast<unsigned long long*>(C.counters.p);
+        HIP_TRY(hipMemsetAsync(dc, 0, 24, stream));
+        HIP_TRY(launch_leaf_classes(static_cast<const LeafDesc*>(C.leaves.p), nleaves,
+                                    static_cast<LeafDesc*>(C.leaves_cls.p), nleaves, caps, dc,
+                                    stream));
+        HIP_TRY(hipMemcpyAsync(hc, dc, 24, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const uint64_t count[3] = {hc[0], hc[1], hc[2]};
+        if (count[0] + count[1] + count[2] != nleaves) return SHUF_EHIP;
+        HIP_TRY(launch_leaf(w, buf, static_cast<const LeafDesc*>(C.leaves_cls.p), count, nleaves,
+                            seed, prm, caps, stream));
     }
     if (!gfy.empty()) {
         HIP_TRY(upload(C.gfy, C.h_gfy, gfy, stream));

@@ -18,8 +18,9 @@ namespace ipss {
 
 namespace {
 
-constexpr uint32_t kRounds = 32;                  // index rounds held in registers
-constexpr uint32_t kWaveSegMax = 64u * kRounds;   // largest segment split by one wave
+// ROUNDS (a template parameter) bounds the index rounds a thread holds in
+// registers: a leaf has at most kThreads * ROUNDS items, and one wave splits
+// segments of up to 64 * ROUNDS items.
 
 __device__ __forceinline__ uint32_t seg_start(uint32_t e) { return e & 0xFFFFu; }
 __device__ __forceinline__ uint32_t seg_len(uint32_t e) { return e >> 16; }
@@ -75,7 +76,7 @@ __device__ __forceinline__ void fy_segment(uint16_t* idx, uint32_t s0, uint32_t 
 
 // Whole-workgroup stable split of segment [s0, s0 + len) by KAPPA-bit labels;
 // children (start, length) go to out[0..k).
-template <int KAPPA>
+template <int KAPPA, int ROUNDS>
 __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* lab, uint32_t* H,
                                                 uint32_t hs, uint32_t* out, uint32_t s0,
                                                 uint32_t len, uint32_t tid, uint32_t wv,
@@ -89,9 +90,9 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
     const uint32_t first = s0 + wv * per_wave + lane;
     for (uint32_t j = tid; j < (kWaves + 1) * hs; j += kThreads) H[j] = 0;
     __syncthreads();
-    uint32_t pk[kRounds];
+    uint32_t pk[ROUNDS];
 #pragma unroll
-    for (uint32_t r = 0; r < kRounds; ++r) {
+    for (uint32_t r = 0; r < static_cast<uint32_t>(ROUNDS); ++r) {
         const uint32_t x = first + 64u * r;
         uint32_t v = 0;
         if (r < rounds && x < end) {
@@ -120,7 +121,7 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
     for (uint32_t l = tid; l < k; l += kThreads)
         out[l] = seg_pack(s0 + Htot[l], Htot[l + 1] - Htot[l]);
 #pragma unroll
-    for (uint32_t r = 0; r < kRounds; ++r) {
+    for (uint32_t r = 0; r < static_cast<uint32_t>(ROUNDS); ++r) {
         const uint32_t x = first + 64u * r;
         if (r < rounds && x < end) {
             const uint32_t l = lab[x] >> sh;
@@ -130,8 +131,8 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
     __syncthreads();
 }
 
-// One wave's stable split of segment [s0, s0 + len), len <= kWaveSegMax.
-template <int KAPPA>
+// One wave's stable split of segment [s0, s0 + len), len <= 64 * ROUNDS.
+template <int KAPPA, int ROUNDS>
 __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, uint32_t* Hw,
                                            uint32_t* out, uint32_t s0, uint32_t len,
                                            uint32_t lane)
@@ -140,9 +141,9 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
     const uint32_t end = s0 + len;
     for (uint32_t j = lane; j <= k; j += 64) Hw[j] = 0;
     const uint32_t rounds = (len + 63) / 64;
-    uint32_t pk[kRounds];
+    uint32_t pk[ROUNDS];
 #pragma unroll
-    for (uint32_t r = 0; r < kRounds; ++r) {
+    for (uint32_t r = 0; r < static_cast<uint32_t>(ROUNDS); ++r) {
         const uint32_t x = s0 + 64u * r + lane;
         uint32_t v = 0;
         if (r < rounds && x < end) {
@@ -158,7 +159,7 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
     wave_exclusive_scan(Hw, k);
     for (uint32_t l = lane; l < k; l += 64) out[l] = seg_pack(s0 + Hw[l], Hw[l + 1] - Hw[l]);
 #pragma unroll
-    for (uint32_t r = 0; r < kRounds; ++r) {
+    for (uint32_t r = 0; r < static_cast<uint32_t>(ROUNDS); ++r) {
         const uint32_t x = s0 + 64u * r + lane;
         if (r < rounds && x < end) {
             const uint32_t l = lab[x] >> sh;
@@ -167,18 +168,22 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
     }
 }
 
-template <typename E, int EMAX>
-__global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
-                                                      const LeafDesc* __restrict__ leaves,
-                                                      uint64_t seed, Params prm)
+// One size class of leaves: at most kThreads * ROUNDS items each, LDS laid
+// out for the class capacity `cap`, MINW waves per SIMD.
+template <typename E, int ROUNDS, int MINW>
+__global__ __launch_bounds__(kThreads, MINW) void k_leaf(uint8_t* __restrict__ buf,
+                                                         const LeafDesc* __restrict__ leaves,
+                                                         uint64_t seed, Params prm, uint32_t cap)
 {
+    constexpr int EMAX = ROUNDS;
+    constexpr uint32_t kWaveSegMax = 64u * ROUNDS;  // largest segment split by one wave
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const LeafDesc ld = leaves[blockIdx.x];
     const uint32_t m = static_cast<uint32_t>(ld.m);
     const uint32_t kmax = 1u << prm.kmax_log2;
     const uint32_t hs = kmax + 1;  // row stride of the counters
-    const LeafLayout LL = leaf_layout(prm.tile, sizeof(E), kmax, prm.n0);
+    const LeafLayout LL = leaf_layout(cap, sizeof(E), kmax, prm.n0);
     uint16_t* idx = reinterpret_cast<uint16_t*>(smem + LL.idx);
     uint8_t* labraw = smem + LL.lab;
     uint32_t* H = reinterpret_cast<uint32_t*>(smem + LL.hist);
@@ -284,14 +289,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
             const uint32_t s0 = seg_start(e), len = seg_len(e);
             uint32_t* out = nxt + tmpk[i];
             switch (kappa_in_tile(len, prm)) {
-            case 1: split_workgroup<1>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 2: split_workgroup<2>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 3: split_workgroup<3>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 4: split_workgroup<4>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 5: split_workgroup<5>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 6: split_workgroup<6>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 7: split_workgroup<7>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            default: split_workgroup<8>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 1: split_workgroup<1, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 2: split_workgroup<2, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 3: split_workgroup<3, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 4: split_workgroup<4, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 5: split_workgroup<5, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 6: split_workgroup<6, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            case 7: split_workgroup<7, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            default: split_workgroup<8, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
             }
         }
 
@@ -303,14 +308,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_leaf(uint8_t* __restrict__ buf,
             uint32_t* Hw = H + wv * hs;
             uint32_t* out = nxt + tmpk[i];
             switch (kappa_in_tile(len, prm)) {
-            case 1: split_wave<1>(idx, lab, Hw, out, s0, len, lane); break;
-            case 2: split_wave<2>(idx, lab, Hw, out, s0, len, lane); break;
-            case 3: split_wave<3>(idx, lab, Hw, out, s0, len, lane); break;
-            case 4: split_wave<4>(idx, lab, Hw, out, s0, len, lane); break;
-            case 5: split_wave<5>(idx, lab, Hw, out, s0, len, lane); break;
-            case 6: split_wave<6>(idx, lab, Hw, out, s0, len, lane); break;
-            case 7: split_wave<7>(idx, lab, Hw, out, s0, len, lane); break;
-            default: split_wave<8>(idx, lab, Hw, out, s0, len, lane); break;
+            case 1: split_wave<1, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
+            case 2: split_wave<2, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
+            case 3: split_wave<3, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
+            case 4: split_wave<4, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
+            case 5: split_wave<5, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
+            case 6: split_wave<6, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
+            case 7: split_wave<7, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
+            default: split_wave<8, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
             }
         }
         __syncthreads();
@@ -373,15 +378,53 @@ __global__ void k_fy_global(uint8_t* __restrict__ buf, const LeafDesc* __restric
     }
 }
 
+// Leaf size classes of an element type: capacities (items) of the small and
+// medium classes for the largest tile, and their register rounds.
 template <typename E>
-hipError_t leaf_t(uint8_t* buf, const LeafDesc* leaves, uint64_t n, uint64_t seed, const Params& prm,
-                  hipStream_t stream)
+struct LeafClasses {
+    static constexpr uint32_t kTmax = kTileBytesMax / sizeof(E);
+    static constexpr int kRoundsL = static_cast<int>(kTmax / kThreads);
+    static constexpr int kRoundsM = static_cast<int>((kTmax / 2 + kTmax / 32 + kThreads - 1) / kThreads);
+    static constexpr int kRoundsS = static_cast<int>((kTmax / 4 + kTmax / 32 + kThreads - 1) / kThreads);
+};
+
+template <typename E, int ROUNDS, int MINW>
+hipError_t leaf_class_t(uint8_t* buf, const LeafDesc* leaves, uint64_t n, uint64_t seed,
+                        const Params& prm, uint32_t cap, hipStream_t stream)
 {
-    constexpr int EMAX = static_cast<int>(kTileBytesMax / (sizeof(E) * kThreads));
-    const LeafLayout LL = leaf_layout(prm.tile, sizeof(E), 1u << prm.kmax_log2, prm.n0);
-    hipLaunchKernelGGL((k_leaf<E, EMAX>), dim3(static_cast<uint32_t>(n)), dim3(kThreads), LL.total,
-                       stream, buf, leaves, seed, prm);
+    if (n == 0) return hipSuccess;
+    if (cap > static_cast<uint32_t>(ROUNDS) * kThreads) return hipErrorInvalidValue;
+    const LeafLayout LL = leaf_layout(cap, sizeof(E), 1u << prm.kmax_log2, prm.n0);
+    hipLaunchKernelGGL((k_leaf<E, ROUNDS, MINW>), dim3(static_cast<uint32_t>(n)), dim3(kThreads),
+                       LL.total, stream, buf, leaves, seed, prm, cap);
     return hipGetLastError();
+}
+
+template <typename E>
+hipError_t leaf_t(uint8_t* buf, const LeafDesc* leaves, const uint64_t* count, uint64_t stride,
+                  uint64_t seed, const Params& prm, const uint32_t* caps, hipStream_t stream)
+{
+    using LC = LeafClasses<E>;
+    hipError_t e;
+    e = leaf_class_t<E, LC::kRoundsS, 8>(buf, leaves, count[0], seed, prm, caps[0], stream);
+    if (e != hipSuccess) return e;
+    e = leaf_class_t<E, LC::kRoundsM, 6>(buf, leaves + stride, count[1], seed, prm, caps[1], stream);
+    if (e != hipSuccess) return e;
+    return leaf_class_t<E, LC::kRoundsL, 4>(buf, leaves + 2 * stride, count[2], seed, prm, caps[2],
+                                            stream);
+}
+
+// Sort leaves into the three classes (order inside a class is immaterial:
+// every leaf is finished independently).
+__global__ void k_leaf_classes(const LeafDesc* __restrict__ in, uint64_t n,
+                               LeafDesc* __restrict__ out, uint64_t stride, uint32_t cap_s,
+                               uint32_t cap_m, unsigned long long* __restrict__ count)
+{
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const LeafDesc d = in[i];
+    const uint32_t c = d.m <= cap_s ? 0u : (d.m <= cap_m ? 1u : 2u);
+    out[c * stride + atomicAdd(&count[c], 1ull)] = d;
 }
 
 template <typename E>
@@ -394,32 +437,68 @@ hipError_t fy_t(uint8_t* buf, const LeafDesc* items, uint64_t n, uint64_t seed, 
 
 }  // namespace
 
-hipError_t launch_leaf(uint32_t w, uint8_t* buf, const LeafDesc* leaves, uint64_t nleaves,
-                       uint64_t seed, const Params& prm, hipStream_t stream)
+void leaf_class_caps(uint32_t w, const Params& prm, uint32_t* caps)
 {
-    if (nleaves == 0) return hipSuccess;
+    uint32_t rs = 0, rm = 0;
     switch (w) {
-    case 4: return leaf_t<uint32_t>(buf, leaves, nleaves, seed, prm, stream);
-    case 8: return leaf_t<uint64_t>(buf, leaves, nleaves, seed, prm, stream);
-    case 16: return leaf_t<Elem16>(buf, leaves, nleaves, seed, prm, stream);
+    case 4: rs = LeafClasses<uint32_t>::kRoundsS; rm = LeafClasses<uint32_t>::kRoundsM; break;
+    case 8: rs = LeafClasses<uint64_t>::kRoundsS; rm = LeafClasses<uint64_t>::kRoundsM; break;
+    default: rs = LeafClasses<Elem16>::kRoundsS; rm = LeafClasses<Elem16>::kRoundsM; break;
+    }
+    const uint32_t T = prm.tile, big = T - (1u << prm.kmax_log2);
+    uint32_t cm = T / 2 + T / 32, cs = T / 4 + T / 32;
+    if (cm > rm * kThreads) cm = rm * kThreads;
+    if (cs > rs * kThreads) cs = rs * kThreads;
+    if (cm > big) cm = big;
+    if (cs > cm) cs = cm;
+    caps[0] = cs;
+    caps[1] = cm;
+    caps[2] = big;
+}
+
+hipError_t launch_leaf_classes(const LeafDesc* in, uint64_t n, LeafDesc* out, uint64_t stride,
+                               const uint32_t* caps, unsigned long long* count, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_leaf_classes, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0,
+                       stream, in, n, out, stride, caps[0], caps[1], count);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf(uint32_t w, uint8_t* buf, const LeafDesc* leaves, const uint64_t* count,
+                       uint64_t stride, uint64_t seed, const Params& prm, const uint32_t* caps,
+                       hipStream_t stream)
+{
+    switch (w) {
+    case 4: return leaf_t<uint32_t>(buf, leaves, count, stride, seed, prm, caps, stream);
+    case 8: return leaf_t<uint64_t>(buf, leaves, count, stride, seed, prm, caps, stream);
+    case 16: return leaf_t<Elem16>(buf, leaves, count, stride, seed, prm, caps, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
+template <typename E>
+static hipError_t leaf_limits_t()
+{
+    using LC = LeafClasses<E>;
+    hipError_t e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<E, LC::kRoundsS, 8>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<E, LC::kRoundsM, 6>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<E, LC::kRoundsL, 4>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+}
+
 hipError_t set_leaf_lds_limits()
 {
-    constexpr int E4 = static_cast<int>(kTileBytesMax / (4 * kThreads));
-    constexpr int E8 = static_cast<int>(kTileBytesMax / (8 * kThreads));
-    constexpr int E16 = static_cast<int>(kTileBytesMax / (16 * kThreads));
-    hipError_t e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<uint32_t, E4>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    hipError_t e = leaf_limits_t<uint32_t>();
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<uint64_t, E8>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    e = leaf_limits_t<uint64_t>();
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<Elem16, E16>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    return leaf_limits_t<Elem16>();
 }
 
 hipError_t launch_fy_global(uint32_t w, uint8_t* buf, const LeafDesc* items, uint64_t count,

@@ -24,8 +24,8 @@ namespace ipss {
 namespace {
 
 // Stable ranks of one wave's rounds for KAPPA-bit labels.  Round r gives lane
-// l the read-order slot first + 64r; pk[r] receives label | rank << 8 where
-// rank counts earlier items of the wave with the same label.
+// l the staging slot first + 64r; pk[r] receives label | rank << 8 where rank
+// counts earlier items of the wave with the same label.
 template <int KAPPA, int R>
 __device__ __forceinline__ void rank_rounds(const uint8_t* lab, uint32_t* Hw, uint32_t first,
                                             uint32_t ts, uint32_t (&pk)[R])
@@ -60,13 +60,16 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(uint8_t* __restrict__ buf
     const uint64_t t = g - sd.tile_off;
     const uint32_t kappa = sd.kappa, k = 1u << kappa;
     const uint32_t kmax = 1u << prm.kmax_log2;
+    const uint32_t hs = k + 1;  // row stride of the per-wave counters
     const RoughLayout L = rough_layout(prm.tile, sizeof(E), kmax);
     constexpr uint32_t kWordsPerElem = sizeof(E) / 4;
 
     E* stage = reinterpret_cast<E*>(smem);
     uint8_t* lab = smem;                                                  // overlays stage
     uint16_t* fs = reinterpret_cast<uint16_t*>(smem);                    // overlays lab
-    uint32_t* H = reinterpret_cast<uint32_t*>(smem + align16(prm.tile)); // overlays stage
+    uint32_t* H = reinterpret_cast<uint32_t*>(smem + L.counts);          // overlays stage
+    uint2* WT = reinterpret_cast<uint2*>(smem + L.slot_tab);              // overlays stage
+    uint8_t* bpiece = smem + L.bpiece;
     uint64_t* lo = reinterpret_cast<uint64_t*>(smem + L.tables);
     uint32_t* qoff = reinterpret_cast<uint32_t*>(lo + kmax + 1);
     uint32_t* cap = qoff + kmax + 1;
@@ -74,7 +77,6 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(uint8_t* __restrict__ buf
     uint32_t* ovt = fill + kmax + 1;
     uint32_t* hot = ovt + kmax + 1;
     uint32_t* nblk = hot + kmax + 1;
-    const uint32_t hs = k + 1;  // row stride of the per-wave counters
 
     E* X = reinterpret_cast<E*>(buf) + sd.elem_off + sd.base;
     const uint64_t pbase = sd.base;
@@ -100,6 +102,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(uint8_t* __restrict__ buf
     __syncthreads();
     const uint32_t ts = qoff[k];
     const uint32_t nblocks = nblk[k];
+    for (uint32_t b = wv; b < k; b += kWaves) {
+        const uint32_t b0 = nblk[b], nb = nblk[b + 1] - b0;
+        for (uint32_t j = lane; j < nb; j += 64) bpiece[b0 + j] = static_cast<uint8_t>(b);
+    }
 
     // Pieces -> staging, one contiguous run each, straight into LDS.
     {
@@ -129,19 +135,28 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(uint8_t* __restrict__ buf
     }
     __syncthreads();  // staging is free: labels and per-wave counters overlay it
 
+    // Labels in staging order: block i of the tile belongs to piece
+    // bpiece[i]; d is the offset of its first position from the piece start.
+    const uint32_t sh = 8 - kappa;
     for (uint32_t i = tid; i < nblocks; i += kThreads) {
-        const uint32_t b = upper_index(nblk, k, i);
+        const uint32_t b = bpiece[i];
         const uint64_t p0 = pbase + lo[b];
-        const uint64_t p1 = p0 + cap[b];
         const uint64_t B = (p0 >> 4) + (i - nblk[b]);
         const Word4 v = label_block(key, sd.level, B);
-        const uint32_t qb = qoff[b];
+        const int32_t d = static_cast<int32_t>(static_cast<uint32_t>(B << 4) - static_cast<uint32_t>(p0));
+        const uint32_t c = cap[b];
+        const int32_t q0 = static_cast<int32_t>(qoff[b]) + d;
+        if (d >= 0 && static_cast<uint32_t>(d) + 16u <= c) {
+            uint8_t* out = lab + q0;
 #pragma unroll
-        for (uint32_t j = 0; j < 16; ++j) {
-            const uint64_t p = B * 16 + j;
-            if (p >= p0 && p < p1)
-                lab[qb + static_cast<uint32_t>(p - p0)] =
-                    static_cast<uint8_t>(block_byte(v, j) >> (8 - kappa));
+            for (uint32_t j = 0; j < 16; ++j)
+                out[j] = static_cast<uint8_t>(__builtin_amdgcn_ubfe(word_of(v, j >> 2), 8 * (j & 3) + sh, kappa));
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < 16; ++j)
+                if (static_cast<uint32_t>(d + static_cast<int32_t>(j)) < c)
+                    lab[q0 + static_cast<int32_t>(j)] =
+                        static_cast<uint8_t>(__builtin_amdgcn_ubfe(word_of(v, j >> 2), 8 * (j & 3) + sh, kappa));
         }
     }
     for (uint32_t i = tid; i < kWaves * hs; i += kThreads) H[i] = 0;
@@ -180,7 +195,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(uint8_t* __restrict__ buf
     if (wv == 1) wave_exclusive_scan(hot, k);
     __syncthreads();
 
-    // Free slots of the pieces, in order, as a list (the label area is dead).
+    // Free slots of the pieces, in order, as a list (the label area is dead),
+    // and the slot table of every (wave, label): an item of rank rr within
+    // its wave is placed at A + rr if rr < B, else it is staged item C + rr
+    // of the tile (A = piece start + earlier waves' count, B = capacity left
+    // to the wave, C = staged items of smaller labels - B).
     const uint32_t nfree = hot[k];
     const bool use_list = nfree <= prm.tile / 2;
     if (use_list) {
@@ -189,30 +208,47 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(uint8_t* __restrict__ buf
             for (uint32_t j = lane; j < nh; j += 64) fs[base + j] = static_cast<uint16_t>(f0 + j);
         }
     }
+    for (uint32_t i = tid; i < kWaves * k; i += kThreads) {
+        const uint32_t w = i >> kappa, l = i & (k - 1);
+        const uint32_t h = H[w * hs + l];
+        const int32_t B = static_cast<int32_t>(cap[l]) - static_cast<int32_t>(h);
+        const uint32_t A = qoff[l] + h;
+        WT[w * k + l] = make_uint2((A & 0xFFFFu) | (static_cast<uint32_t>(B) << 16),
+                                   ovt[l] - static_cast<uint32_t>(B));
+    }
     __syncthreads();
 
-    // Destination slot in read order: placed items at the front of their
-    // label's piece; staged items, ordered by (label, rank), into the free
-    // slots of the pieces taken in order.
+    // Destination slot in staging order.
+    if (use_list) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t q = first + 64u * r;
-        if (q < ts) {
-            const uint32_t l = pk[r] & 0xFFu;
-            const uint32_t rr = H[wv * hs + l] + (pk[r] >> 8);
-            uint32_t slot;
-            if (rr < cap[l]) {
-                slot = qoff[l] + rr;
-            } else {
-                const uint32_t s = ovt[l] + (rr - cap[l]);
-                if (use_list) {
-                    slot = fs[s];
+        for (int r = 0; r < R; ++r) {
+            const uint32_t q = first + 64u * r;
+            if (q < ts) {
+                const uint32_t l = pk[r] & 0xFFu, rr = pk[r] >> 8;
+                const uint2 e = WT[wv * k + l];
+                const bool placed = static_cast<int32_t>(rr) < (static_cast<int32_t>(e.x) >> 16);
+                const uint32_t f = fs[placed ? 0u : e.y + rr];
+                pk[r] = placed ? (e.x & 0xFFFFu) + rr : f;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t q = first + 64u * r;
+            if (q < ts) {
+                const uint32_t l = pk[r] & 0xFFu, rr = pk[r] >> 8;
+                const uint2 e = WT[wv * k + l];
+                const int32_t B = static_cast<int32_t>(e.x) >> 16;
+                uint32_t slot;
+                if (static_cast<int32_t>(rr) < B) {
+                    slot = (e.x & 0xFFFFu) + rr;
                 } else {
+                    const uint32_t s = e.y + rr;
                     const uint32_t bb = upper_index(hot, k, s);
                     slot = qoff[bb] + fill[bb] + (s - hot[bb]);
                 }
+                pk[r] = slot;
             }
-            pk[r] = slot;
         }
     }
     __syncthreads();  // labels, free list and counters are dead from here on

@@ -59,9 +59,15 @@ hipError_t launch_gather(uint32_t w, uint8_t* buf, uint8_t* ws, const LevelTable
 hipError_t launch_scatter(uint32_t w, uint8_t* buf, const uint8_t* ws, const LevelTables& t,
                           hipStream_t stream);
 
-// Subproblems that fit a tile: in-LDS levels and Fisher-Yates.
-hipError_t launch_leaf(uint32_t w, uint8_t* buf, const LeafDesc* leaves, uint64_t nleaves,
-                       uint64_t seed, const Params& prm, hipStream_t stream);
+// Subproblems that fit a tile: in-LDS levels and Fisher-Yates, launched per
+// size class (small, medium, large: caps[0..2] items, LDS sized to match).
+void leaf_class_caps(uint32_t w, const Params& prm, uint32_t* caps);
+hipError_t launch_leaf_classes(const LeafDesc* in, uint64_t n, LeafDesc* out, uint64_t stride,
+                               const uint32_t* caps, unsigned long long* count, hipStream_t stream);
+// leaves of class c are leaves[c * stride, c * stride + count[c])
+hipError_t launch_leaf(uint32_t w, uint8_t* buf, const LeafDesc* leaves, const uint64_t* count,
+                       uint64_t stride, uint64_t seed, const Params& prm, const uint32_t* caps,
+                       hipStream_t stream);
 hipError_t set_leaf_lds_limits();
 // Sequential Fisher-Yates in global memory (recursion cap reached on a
 // subproblem that does not fit a tile).
