@@ -26,6 +26,8 @@
  *   - `stream` is a hipStream_t (NULL = the null stream).  The work runs on
  *     that stream; the call returns after it has completed (the library
  *     synchronises the stream to plan each recursion level);
+ *   - device memory is addressed absolutely: every array, wherever it lives,
+ *     is reached through its own pointer;
  *   - argument errors are detected before any GPU work starts, and then the
  *     data is untouched; after SHUF_EHIP the contents are unspecified;
  *   - calls may come from several host threads; calls on one device are
@@ -99,6 +101,59 @@ int shuffle_inplace_ex(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed
  * alignment), SHUF_EUNSUPPORTED, SHUF_ENOMEM, SHUF_EHIP. */
 int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
                     uint64_t seed, void* stream);
+
+/* One array of a multi-array call or a serving request: n elements at device
+ * pointer ptr (aligned to elem_bytes; may be NULL if n <= 1), shuffled with
+ * its own seed and stream id. */
+typedef struct {
+    void* ptr;
+    uint64_t n;
+    uint64_t seed;
+    uint32_t stream_id;
+    uint32_t reserved;
+} shuf_array_t;
+
+/* Shuffle `count` independent arrays, each in place and anywhere in device
+ * memory: array j is shuffled exactly as shuffle_inplace_ex(arrays[j].ptr,
+ * arrays[j].n, elem_bytes, arrays[j].seed, arrays[j].stream_id, default
+ * params).  All arrays are processed together, level by level, in shared
+ * launches.  Arrays must not overlap.  `arrays` is a HOST array.
+ * Errors: SHUF_EINVAL (NULL arrays with count > 0, bad width, NULL or
+ * misaligned ptr with n > 1), SHUF_EUNSUPPORTED, SHUF_ENOMEM, SHUF_EHIP. */
+int shuffle_many(const shuf_array_t* arrays, uint64_t count, uint32_t elem_bytes, void* stream);
+
+/* Continuous batching.  A session accepts shuffle requests at any time and
+ * advances all of them together, one step per call: a step gives every
+ * in-flight request's pending subproblems one recursion level in shared
+ * launches and finishes every pending subproblem that fits a tile.  Requests
+ * submitted between steps join at the next step.  Each request's result is
+ * exactly shuffle_inplace_ex(ptr, n, elem_bytes, seed, stream_id, default
+ * params), whatever else is in flight (the permutation is a function of the
+ * request alone).
+ *   shuf_session_create   session for elements of elem_bytes on the current
+ *                         device (later calls must run with that device
+ *                         current); *out receives the handle
+ *   shuf_session_submit   queue a request; the caller keeps ptr valid and does
+ *                         not touch its data until the ticket is reported done;
+ *                         *ticket receives a positive id
+ *   shuf_session_step     run one step on `stream` (blocking, as the other
+ *                         calls) if anything is in flight, then report up to
+ *                         `cap` completed tickets in done[0..*ndone); further
+ *                         completions are reported by later calls
+ *   shuf_session_inflight requests submitted and not yet complete, and
+ *                         completed tickets not yet reported (may be NULL)
+ *   shuf_session_destroy  waits for the device and frees the session (requests
+ *                         still in flight are abandoned, their data unspecified)
+ * A session is used by one host thread at a time; steps of sessions and other
+ * calls on one device are serialised by the library.  After a step fails with
+ * SHUF_EHIP the session only returns SHUF_EHIP.  Errors otherwise as above. */
+typedef struct shuf_session shuf_session_t;
+int shuf_session_create(uint32_t elem_bytes, shuf_session_t** out);
+int shuf_session_submit(shuf_session_t* s, const shuf_array_t* a, uint64_t* ticket);
+int shuf_session_step(shuf_session_t* s, void* stream, uint64_t* done, uint64_t cap,
+                      uint64_t* ndone);
+int shuf_session_inflight(const shuf_session_t* s, uint64_t* inflight, uint64_t* completed_unread);
+int shuf_session_destroy(shuf_session_t* s);
 
 /* Human-readable text of an error code (static storage). */
 const char* shuffle_strerror(int code);

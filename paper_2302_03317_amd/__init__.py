@@ -56,6 +56,16 @@ class _KernelTime(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_uint64), ("bytes", ctypes.c_double)]
 
 
+class _Array(ctypes.Structure):
+    _fields_ = [
+        ("ptr", ctypes.c_void_p),
+        ("n", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64),
+        ("stream_id", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
 KERNEL_KINDS = ("rough", "tables", "gather", "scatter", "leaf", "fy_fallback")
 
 
@@ -94,6 +104,18 @@ def lib() -> ctypes.CDLL:
         L.shuffle_inplace_ex.restype = i
         L.shuffle_batched.argtypes = [vp, ctypes.POINTER(u64), u64, u32, u64, vp]
         L.shuffle_batched.restype = i
+        L.shuffle_many.argtypes = [ctypes.POINTER(_Array), u64, u32, vp]
+        L.shuffle_many.restype = i
+        L.shuf_session_create.argtypes = [u32, ctypes.POINTER(vp)]
+        L.shuf_session_create.restype = i
+        L.shuf_session_submit.argtypes = [vp, ctypes.POINTER(_Array), ctypes.POINTER(u64)]
+        L.shuf_session_submit.restype = i
+        L.shuf_session_step.argtypes = [vp, vp, ctypes.POINTER(u64), u64, ctypes.POINTER(u64)]
+        L.shuf_session_step.restype = i
+        L.shuf_session_inflight.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.shuf_session_inflight.restype = i
+        L.shuf_session_destroy.argtypes = [vp]
+        L.shuf_session_destroy.restype = i
         L.shuffle_strerror.argtypes = [i]
         L.shuffle_strerror.restype = ctypes.c_char_p
         L.shuffle_last_stats.argtypes = [ctypes.POINTER(_Stats)]
@@ -181,6 +203,105 @@ def shuffle_batched(tensor, offsets, seed: int, stream=None) -> None:
     )
     if rc != SHUF_OK:
         raise ShuffleError(rc, "shuffle_batched")
+
+
+def _array(tensor, seed: int, stream_id: int) -> _Array:
+    n, w = _geometry(tensor)
+    return _Array(ctypes.c_void_p(tensor.data_ptr()), n, seed & (2**64 - 1), stream_id & (2**32 - 1), 0), w
+
+
+def shuffle_many(tensors, seeds, stream_ids, stream=None) -> None:
+    """Shuffle several GPU tensors (same row width, any allocations) in place,
+    tensor j with seeds[j] and stream_ids[j] and default parameters, all in
+    shared launches."""
+    tensors = list(tensors)
+    if not tensors:
+        return
+    arrs = []
+    width = None
+    for t, sd, sid in zip(tensors, seeds, stream_ids, strict=True):
+        a, w = _array(t, sd, sid)
+        if width is None:
+            width = w
+        elif w != width:
+            raise ValueError("all tensors must have the same row width")
+        arrs.append(a)
+    buf = (_Array * len(arrs))(*arrs)
+    rc = lib().shuffle_many(buf, len(arrs), width, _stream_handle(tensors[0], stream))
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_many")
+
+
+class Session:
+    """Continuous batching: submit(tensor, seed, stream_id) queues a request;
+    step() advances every request in flight by one recursion level (new
+    requests join at the next step) and returns the tickets completed."""
+
+    def __init__(self, elem_bytes: int, device=None):
+        import torch
+
+        self._torch = torch
+        self.elem_bytes = elem_bytes
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = lib().shuf_session_create(elem_bytes, ctypes.byref(h))
+        if rc != SHUF_OK:
+            raise ShuffleError(rc, "shuf_session_create")
+        self._h = h
+        self._keep = {}  # ticket -> tensor, kept alive while in flight
+
+    def submit(self, tensor, seed: int, stream_id: int = 0) -> int:
+        a, w = _array(tensor, seed, stream_id)
+        if w != self.elem_bytes:
+            raise ValueError(f"row width {w} != session width {self.elem_bytes}")
+        t = ctypes.c_uint64()
+        rc = lib().shuf_session_submit(self._h, ctypes.byref(a), ctypes.byref(t))
+        if rc != SHUF_OK:
+            raise ShuffleError(rc, "shuf_session_submit")
+        self._keep[int(t.value)] = tensor
+        return int(t.value)
+
+    def step(self, stream=None, cap: int = 4096) -> list:
+        done = (ctypes.c_uint64 * cap)()
+        nd = ctypes.c_uint64()
+        if stream is None:
+            stream = self._torch.cuda.current_stream(self.device)
+        sh = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        with self._torch.cuda.device(self.device):
+            rc = lib().shuf_session_step(self._h, sh, done, cap, ctypes.byref(nd))
+        if rc != SHUF_OK:
+            raise ShuffleError(rc, "shuf_session_step")
+        out = [int(done[i]) for i in range(nd.value)]
+        for t in out:
+            self._keep.pop(t, None)
+        return out
+
+    def inflight(self) -> tuple:
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        rc = lib().shuf_session_inflight(self._h, ctypes.byref(a), ctypes.byref(b))
+        if rc != SHUF_OK:
+            raise ShuffleError(rc, "shuf_session_inflight")
+        return int(a.value), int(b.value)
+
+    def close(self) -> None:
+        if self._h:
+            with self._torch.cuda.device(self.device):
+                lib().shuf_session_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def last_stats() -> dict:

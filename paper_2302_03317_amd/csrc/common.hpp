@@ -21,9 +21,18 @@ struct Params {
     uint32_t lmax;      // recursion cap
 };
 
+// Elements are addressed absolutely: an array at device address A holds
+// element i at element address A / w + i (arrays are aligned to w), so one
+// launch can serve arrays of any number of allocations.
+template <typename E>
+__host__ __device__ __forceinline__ E* elem_ptr(uint64_t elem_addr)
+{
+    return reinterpret_cast<E*>(static_cast<uintptr_t>(elem_addr * sizeof(E)));
+}
+
 // One subproblem of the tiled regime at the current level.
 struct SubDesc {
-    uint64_t elem_off;  // start of its array in the buffer, in elements
+    uint64_t elem_off;  // element address of its array's first element
     uint64_t base;      // start of the subproblem inside its array (positions)
     uint64_t m;         // elements
     uint64_t tiles;     // P
@@ -31,19 +40,25 @@ struct SubDesc {
     uint64_t tab_off;   // first entry of its per-(tile, bucket) tables (row = tile)
     uint64_t chunk_off; // first chunk of its table scans
     uint64_t chtab_off; // first entry of its per-(chunk, bucket) tables (row = chunk)
+    uint64_t seed;      // Philox key of its array
     uint32_t bk_off;    // first entry of its per-bucket tables
     uint32_t kappa;     // k = 2^kappa
     uint32_t level;
     uint32_t stream_id;
+    uint32_t owner;     // request the array belongs to (host bookkeeping)
+    uint32_t pad;
 };
 
 // One subproblem finished in LDS (fits a tile) or by the sequential fallback.
 struct LeafDesc {
-    uint64_t elem_off;
-    uint64_t base;
+    uint64_t elem_off;  // element address of its array's first element
+    uint64_t base;      // start inside its array (positions)
     uint64_t m;
+    uint64_t seed;
     uint32_t level;
     uint32_t stream_id;
+    uint32_t owner;
+    uint32_t pad;
 };
 
 // Piece t of equal region b of a subproblem of m elements cut into 2^kappa

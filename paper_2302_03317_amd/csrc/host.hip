@@ -1,16 +1,19 @@
 // Host planner and C ABI of the in-place ScatterShuffle.
 //
-// The recursion of arXiv 2302.03317 (Fig. 2, Theorem 1) is flattened level by
-// level: all subproblems of one level that need the tiled pass share one
-// rough-pass launch, one set of table kernels and one fix-up; all subproblems
-// that fit a tile (from any level, any array) share one LDS leaf launch at
-// the end.  After the tables of a level the host reads the exact bucket sizes
-// (to plan the next level) and the number of movers (to size the workspace).
+// The recursion of arXiv 2302.03317 (Fig. 2, Theorem 1) is flattened into
+// steps: in one step every waiting subproblem that needs the tiled pass gets
+// one level (one shared rough-pass launch, one set of table kernels, one
+// fix-up) and every waiting subproblem that fits a tile is finished in LDS
+// (shared leaf launches by size class), whatever array, request or level it
+// belongs to.  After the tables of a level the host reads the exact bucket
+// sizes (to plan the next step) and the number of movers (to size the
+// workspace).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "common.hpp"
@@ -168,13 +171,8 @@ constexpr int kMaxDevices = 64;
 Context g_ctx[kMaxDevices];
 
 struct HostSub {
-    uint64_t elem_off, base, m;
-    uint32_t level, stream_id;
-};
-
-struct ArraySpec {
-    uint64_t elem_off, n;
-    uint32_t stream_id;
+    uint64_t elem_off, base, m, seed;
+    uint32_t level, stream_id, owner;
 };
 
 uint32_t kappa_of(uint64_t m, bool tiled, const Params& p)
@@ -231,66 +229,128 @@ hipError_t upload(DevBuf& d, HostBuf& h, const std::vector<T>& v, hipStream_t s)
     return hipMemcpyAsync(d.p, h.p, bytes, hipMemcpyHostToDevice, s);
 }
 
-int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
-        const std::vector<ArraySpec>& arrays, hipStream_t stream)
+// Work of one engine: subproblems waiting for a tiled level and leaves
+// waiting for the leaf launch, for any number of arrays ("requests").  One
+// step runs one tiled level of every waiting subproblem and every waiting
+// leaf; their children wait for the next step.  A request is complete after
+// the first step in which it had no tiled subproblem: by then every leaf of
+// it has run.  Blocking calls use a temporary engine; a session keeps one
+// between steps, and new requests join at the next step.
+struct Engine {
+    uint32_t w = 0;
+    Params prm{};
+    std::vector<HostSub> cur;          // tiled subproblems (and fallback items) of the next step
+    std::vector<LeafDesc> new_leaves;  // leaves of newly submitted arrays
+    DevBuf leaves[2];                  // leaf lists: leaves[which] holds those of the next step
+    HostBuf h_new;
+    int which = 0;
+    uint64_t nleaves = 0, leaf_elems = 0;
+    std::vector<uint64_t> ticket;  // owner slot -> ticket (0 = free)
+    std::vector<uint32_t> free_slots;
+    std::vector<uint64_t> done_queue;
+    uint64_t next_ticket = 1, inflight = 0;
+    bool broken = false;
+};
+
+uint64_t engine_submit(Engine& E, uint64_t elem_addr, uint64_t n, uint64_t seed, uint32_t stream_id)
 {
+    uint32_t slot;
+    if (!E.free_slots.empty()) {
+        slot = E.free_slots.back();
+        E.free_slots.pop_back();
+    } else {
+        slot = static_cast<uint32_t>(E.ticket.size());
+        E.ticket.push_back(0);
+    }
+    const uint64_t t = E.next_ticket++;
+    E.ticket[slot] = t;
+    ++E.inflight;
+    const uint64_t tile_limit = E.prm.tile - (1u << E.prm.kmax_log2);
+    if (n >= 2) {
+        if (n > tile_limit) E.cur.push_back({elem_addr, 0, n, seed, 0, stream_id, slot});
+        else E.new_leaves.push_back({elem_addr, 0, n, seed, 0, stream_id, slot, 0});
+    }
+    return t;
+}
+
+// One step (see Engine).  Appends the tickets of completed requests to
+// E.done_queue and adds the step's work to `st`.
+int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
+{
+    if (E.broken) return SHUF_EHIP;
+    const uint32_t w = E.w;
+    const Params& prm = E.prm;
     if (!C.init) {
         HIP_TRY(set_rough_lds_limits());
         HIP_TRY(set_leaf_lds_limits());
         C.init = true;
     }
-    shuf_stats_t st{};
     const uint32_t kmax = 1u << prm.kmax_log2;
     const uint64_t tile_limit = prm.tile - kmax;  // subproblems up to this size finish in LDS
-    C.spans.clear();
-    C.events_used = 0;
     HIP_TRY(C.err.ensure(4));
     HIP_TRY(C.h_err.ensure(4));
     HIP_TRY(hipMemsetAsync(C.err.p, 0, 4, stream));
-    HIP_TRY(C.counters.ensure(24));
-    HIP_TRY(C.h_counters.ensure(24));
+    HIP_TRY(C.counters.ensure(48));
+    HIP_TRY(C.h_counters.ensure(48));
     HIP_TRY(C.total.ensure(8));
     HIP_TRY(C.h_total.ensure(8));
-
-    // Roots: arrays that fit a tile are leaves right away.
-    std::vector<LeafDesc> root_leaves, gfy;
-    std::vector<HostSub> cur;
-    for (const ArraySpec& a : arrays) {
-        if (a.n < 2) continue;
-        if (a.n > tile_limit) cur.push_back({a.elem_off, 0, a.n, 0, a.stream_id});
-        else root_leaves.push_back({a.elem_off, 0, a.n, 0, a.stream_id});
-    }
-    uint64_t nleaves = root_leaves.size();
-    HIP_TRY(upload(C.leaves, C.h_leaves, root_leaves, stream));
+    unsigned long long* dc = static_cast<unsigned long long*>(C.counters.p);
     unsigned long long* hc = C.h_counters.as<unsigned long long>();
-    hc[0] = nleaves;
-    hc[1] = 0;
-    hc[2] = 0;
-    for (const LeafDesc& l : root_leaves) hc[2] += l.m;
-    uint64_t leaf_elems = hc[2];
-    HIP_TRY(hipMemcpyAsync(C.counters.p, hc, 24, hipMemcpyHostToDevice, stream));
+    // [0] leaf children, [1] big children, [2] leaf child elements, [3..5] leaves per class
+    HIP_TRY(hipMemsetAsync(dc, 0, 48, stream));
+
+    std::vector<uint8_t> had_tiled(E.ticket.size(), 0);
+
+    // Leaves of newly submitted arrays join this step's leaf list.
+    if (!E.new_leaves.empty()) {
+        const size_t add = E.new_leaves.size() * sizeof(LeafDesc);
+        DevBuf& L = E.leaves[E.which];
+        HIP_TRY(grow_keep(L, E.nleaves * sizeof(LeafDesc) + add, E.nleaves * sizeof(LeafDesc), stream));
+        HIP_TRY(E.h_new.ensure(add));
+        std::memcpy(E.h_new.p, E.new_leaves.data(), add);
+        HIP_TRY(hipMemcpyAsync(static_cast<uint8_t*>(L.p) + E.nleaves * sizeof(LeafDesc), E.h_new.p,
+                               add, hipMemcpyHostToDevice, stream));
+        for (const LeafDesc& l : E.new_leaves) E.leaf_elems += l.m;
+        E.nleaves += E.new_leaves.size();
+        E.new_leaves.clear();
+    }
+    const uint64_t run_leaves = E.nleaves, run_leaf_elems = E.leaf_elems;
+    const LeafDesc* leaves_now = static_cast<const LeafDesc*>(E.leaves[E.which].p);
+    uint32_t caps[3];
+    leaf_class_caps(w, prm, caps);
+    if (run_leaves) {
+        HIP_TRY(C.leaves_cls.ensure(3 * run_leaves * sizeof(LeafDesc)));
+        HIP_TRY(launch_leaf_classes(leaves_now, run_leaves, static_cast<LeafDesc*>(C.leaves_cls.p),
+                                    run_leaves, caps, dc + 3, stream));
+    }
+
+    // Tiled level of every waiting subproblem; the recursion cap sends a
+    // subproblem to the sequential fallback.
+    std::vector<HostSub> tiled;
+    std::vector<LeafDesc> gfy;
+    for (const HostSub& s : E.cur) {
+        if (s.m <= prm.n0 || s.level >= prm.lmax) {
+            if (s.m > 0xFFFFFFFFull) return SHUF_EUNSUPPORTED;
+            gfy.push_back({s.elem_off, s.base, s.m, s.seed, s.level, s.stream_id, s.owner, 0});
+        } else {
+            tiled.push_back(s);
+            had_tiled[s.owner] = 1;
+        }
+    }
+    E.cur.clear();
 
     std::vector<SubDesc> subs;
     std::vector<uint32_t> tile_sub, chunk_sub, bk_sub;
-    while (!cur.empty()) {
-        std::vector<HostSub> tiled;
-        for (const HostSub& s : cur) {
-            if (s.m <= prm.n0 || s.level >= prm.lmax) gfy.push_back({s.elem_off, s.base, s.m, s.level, s.stream_id});
-            else tiled.push_back(s);
-        }
-        cur.clear();
-        if (tiled.empty()) break;
-
-        subs.clear();
-        tile_sub.clear();
-        chunk_sub.clear();
-        bk_sub.clear();
-        uint64_t ntiles = 0, tab = 0, nchunks = 0, chtab = 0, nbk = 0;
+    LevelTables T{};
+    uint64_t ntiles = 0;
+    if (!tiled.empty()) {
+        uint64_t tab = 0, nchunks = 0, chtab = 0, nbk = 0;
         for (const HostSub& s : tiled) {
             SubDesc d{};
             d.elem_off = s.elem_off;
             d.base = s.base;
             d.m = s.m;
+            d.seed = s.seed;
             d.kappa = kappa_of(s.m, true, prm);
             const uint64_t k = 1ull << d.kappa;
             d.tiles = (s.m + (prm.tile - k) - 1) / (prm.tile - k);
@@ -302,6 +362,7 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
             d.bk_off = static_cast<uint32_t>(nbk);
             d.level = s.level;
             d.stream_id = s.stream_id;
+            d.owner = s.owner;
             const uint64_t nch = (d.tiles + kChunk - 1) / kChunk;
             ntiles += d.tiles;
             tab += d.tiles * k;
@@ -339,11 +400,9 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
         HIP_TRY(C.K.ensure(nbk * 8));
         HIP_TRY(C.MB.ensure(nbk * 8));
         HIP_TRY(C.wsp.ensure((nbk / kScanChunk + 2) * 8));
-        HIP_TRY(grow_keep(C.leaves, (nleaves + nbk) * sizeof(LeafDesc), nleaves * sizeof(LeafDesc),
-                          stream));
+        HIP_TRY(E.leaves[1 - E.which].ensure(nbk * sizeof(LeafDesc)));
         HIP_TRY(C.big.ensure(nbk * sizeof(LeafDesc)));
 
-        LevelTables T{};
         T.subs = static_cast<const SubDesc*>(C.subs.p);
         T.tile_sub = static_cast<const uint32_t*>(C.tile_sub.p);
         T.chunk_sub = static_cast<const uint32_t*>(C.chunk_sub.p);
@@ -365,28 +424,31 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
         T.ntiles = ntiles;
         T.nchunks = nchunks;
         T.nbuckets = nbk;
-
         {
             SpanGuard g(C, stream, 0, 2.0 * level_elems * w);
-            HIP_TRY(launch_rough(w, buf, T.subs, T.tile_sub, T.cnt, ntiles, seed, prm, stream));
+            HIP_TRY(launch_rough(w, T.subs, T.tile_sub, T.cnt, ntiles, prm, stream));
         }
         {
             SpanGuard g(C, stream, 1, 0.0);
             HIP_TRY(launch_tables_sizes(T, stream));
             HIP_TRY(launch_tables_routes(T, stream));
-            unsigned long long* dc = static_cast<unsigned long long*>(C.counters.p);
-            HIP_TRY(hipMemsetAsync(dc + 1, 0, 8, stream));
             HIP_TRY(launch_children(T, static_cast<uint32_t>(tile_limit),
-                                    static_cast<LeafDesc*>(C.leaves.p),
+                                    static_cast<LeafDesc*>(E.leaves[1 - E.which].p),
                                     static_cast<LeafDesc*>(C.big.p), dc, stream));
         }
         HIP_TRY(hipMemcpyAsync(C.h_total.p, T.total, 8, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipMemcpyAsync(hc, C.counters.p, 24, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
+    }
+    HIP_TRY(hipMemcpyAsync(hc, dc, 48, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const uint64_t child_leaves = hc[0], nbig = hc[1], child_elems = hc[2];
+    const uint64_t count[3] = {hc[3], hc[4], hc[5]};
+    if (run_leaves && count[0] + count[1] + count[2] != run_leaves) {
+        E.broken = true;
+        return SHUF_EHIP;
+    }
+
+    if (!tiled.empty()) {
         const uint64_t movers = C.h_total.as<uint64_t>()[0];
-        nleaves = hc[0];
-        leaf_elems = hc[2];
-        const uint64_t nbig = hc[1];
         if (nbig) {
             HIP_TRY(C.h_big.ensure(nbig * sizeof(LeafDesc)));
             HIP_TRY(hipMemcpyAsync(C.h_big.p, C.big.p, nbig * sizeof(LeafDesc),
@@ -394,9 +456,10 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
             HIP_TRY(hipStreamSynchronize(stream));
             const LeafDesc* bl = C.h_big.as<LeafDesc>();
             for (uint64_t i = 0; i < nbig; ++i)
-                cur.push_back({bl[i].elem_off, bl[i].base, bl[i].m, bl[i].level, bl[i].stream_id});
-            // the device appends in no particular order; plan in position order
-            std::sort(cur.begin(), cur.end(), [](const HostSub& a, const HostSub& b) {
+                E.cur.push_back({bl[i].elem_off, bl[i].base, bl[i].m, bl[i].seed, bl[i].level,
+                                 bl[i].stream_id, bl[i].owner});
+            // the device appends in no particular order; plan in address order
+            std::sort(E.cur.begin(), E.cur.end(), [](const HostSub& a, const HostSub& b) {
                 return a.elem_off != b.elem_off ? a.elem_off < b.elem_off : a.base < b.base;
             });
         }
@@ -404,65 +467,85 @@ int run(Context& C, uint8_t* buf, uint32_t w, uint64_t seed, const Params& prm,
         T.ws_cap = movers;
         {
             SpanGuard g(C, stream, 2, 2.0 * movers * w);
-            HIP_TRY(launch_gather(w, buf, static_cast<uint8_t*>(C.ws.p), T, stream));
+            HIP_TRY(launch_gather(w, static_cast<uint8_t*>(C.ws.p), T, stream));
         }
         {
             SpanGuard g(C, stream, 3, 2.0 * movers * w);
-            HIP_TRY(launch_scatter(w, buf, static_cast<const uint8_t*>(C.ws.p), T, stream));
+            HIP_TRY(launch_scatter(w, static_cast<const uint8_t*>(C.ws.p), T, stream));
         }
         st.tiled_levels++;
         st.tiles += ntiles;
         st.movers += movers;
         st.workspace_bytes = std::max<uint64_t>(st.workspace_bytes, movers * w);
     }
-
-    for (const LeafDesc& f : gfy)
-        if (f.m > 0xFFFFFFFFull) return SHUF_EUNSUPPORTED;
-    if (nleaves) {
-        SpanGuard g(C, stream, 4, 2.0 * static_cast<double>(leaf_elems) * w);
-        uint32_t caps[3];
-        leaf_class_caps(w, prm, caps);
-        HIP_TRY(C.leaves_cls.ensure(3 * nleaves * sizeof(LeafDesc)));
-        unsigned long long* dc = static_cast<unsigned long long*>(C.counters.p);
-        HIP_TRY(hipMemsetAsync(dc, 0, 24, stream));
-        HIP_TRY(launch_leaf_classes(static_cast<const LeafDesc*>(C.leaves.p), nleaves,
-                                    static_cast<LeafDesc*>(C.leaves_cls.p), nleaves, caps, dc,
-                                    stream));
-        HIP_TRY(hipMemcpyAsync(hc, dc, 24, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        const uint64_t count[3] = {hc[0], hc[1], hc[2]};
-        if (count[0] + count[1] + count[2] != nleaves) return SHUF_EHIP;
-        HIP_TRY(launch_leaf(w, buf, static_cast<const LeafDesc*>(C.leaves_cls.p), count, nleaves,
-                            seed, prm, caps, stream));
+    if (run_leaves) {
+        SpanGuard g(C, stream, 4, 2.0 * static_cast<double>(run_leaf_elems) * w);
+        HIP_TRY(launch_leaf(w, static_cast<const LeafDesc*>(C.leaves_cls.p), count, run_leaves, prm,
+                            caps, stream));
     }
     if (!gfy.empty()) {
         HIP_TRY(upload(C.gfy, C.h_gfy, gfy, stream));
         uint64_t elems = 0;
         for (const LeafDesc& l : gfy) elems += l.m;
         SpanGuard g(C, stream, 5, 2.0 * elems * w);
-        HIP_TRY(launch_fy_global(w, buf, static_cast<const LeafDesc*>(C.gfy.p), gfy.size(), seed,
-                                 stream));
+        HIP_TRY(launch_fy_global(w, static_cast<const LeafDesc*>(C.gfy.p), gfy.size(), stream));
     }
     HIP_TRY(hipMemcpyAsync(C.h_err.p, C.err.p, 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    if (C.h_err.as<uint32_t>()[0] != 0) return SHUF_EHIP;  // an index check failed in a kernel
+    if (C.h_err.as<uint32_t>()[0] != 0) {  // an index check failed in a kernel
+        E.broken = true;
+        return SHUF_EHIP;
+    }
     if (C.timing) collect_spans(C);
-    st.leaves = nleaves;
-    st.fy_fallback = gfy.size();
-    C.stats = st;
+    st.leaves += run_leaves;
+    st.fy_fallback += gfy.size();
+
+    // Children leaves wait for the next step.
+    E.which = 1 - E.which;
+    E.nleaves = child_leaves;
+    E.leaf_elems = child_elems;
+    for (uint32_t slot = 0; slot < E.ticket.size(); ++slot) {
+        if (E.ticket[slot] == 0 || had_tiled[slot]) continue;
+        E.done_queue.push_back(E.ticket[slot]);
+        E.ticket[slot] = 0;
+        E.free_slots.push_back(slot);
+        --E.inflight;
+    }
     return SHUF_OK;
 }
 
-int run_locked(uint8_t* buf, uint32_t w, uint64_t seed, const shuf_params_t& p,
-               const std::vector<ArraySpec>& arrays, void* stream)
+Context* current_context(int* dev_out = nullptr)
 {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return SHUF_EHIP;
-    if (dev < 0 || dev >= kMaxDevices) return SHUF_EUNSUPPORTED;
-    Context& C = g_ctx[dev];
-    std::lock_guard<std::mutex> lock(C.mu);
-    const Params prm{p.tile, p.kmax_log2, p.n0, p.lmax};
-    return run(C, buf, w, seed, prm, arrays, static_cast<hipStream_t>(stream));
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    if (dev_out) *dev_out = dev;
+    return &g_ctx[dev];
+}
+
+// Run an engine's submitted work to completion (blocking calls).
+int engine_drain(Engine& E, void* stream)
+{
+    Context* C = current_context();
+    if (!C) return SHUF_EHIP;
+    std::lock_guard<std::mutex> lock(C->mu);
+    C->spans.clear();
+    C->events_used = 0;
+    shuf_stats_t st{};
+    while (E.inflight) {
+        const int rc = engine_step(*C, E, static_cast<hipStream_t>(stream), st);
+        if (rc != SHUF_OK) return rc;
+    }
+    C->stats = st;
+    return SHUF_OK;
+}
+
+Engine make_engine(uint32_t w, const shuf_params_t& p)
+{
+    Engine E;
+    E.w = w;
+    E.prm = Params{p.tile, p.kmax_log2, p.n0, p.lmax};
+    return E;
 }
 
 }  // namespace
@@ -495,8 +578,9 @@ int shuffle_inplace_ex(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed
     if (!ptr) return SHUF_EINVAL;
     if (reinterpret_cast<uintptr_t>(ptr) % elem_bytes) return SHUF_EINVAL;
     if (n >= kMaxElements) return SHUF_EUNSUPPORTED;
-    std::vector<ArraySpec> arrays{{0, n, stream_id}};
-    return run_locked(static_cast<uint8_t*>(ptr), elem_bytes, seed, *params, arrays, stream);
+    Engine E = make_engine(elem_bytes, *params);
+    engine_submit(E, reinterpret_cast<uintptr_t>(ptr) / elem_bytes, n, seed, stream_id);
+    return engine_drain(E, stream);
 }
 
 int shuffle_inplace(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream)
@@ -512,15 +596,12 @@ int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t
 {
     if (!valid_width(elem_bytes) || !offsets) return SHUF_EINVAL;
     if (count >= (1ull << 32)) return SHUF_EUNSUPPORTED;
-    std::vector<ArraySpec> arrays;
-    arrays.reserve(count);
     bool any = false;
     for (uint64_t j = 0; j < count; ++j) {
         if (offsets[j + 1] < offsets[j]) return SHUF_EINVAL;
         const uint64_t n = offsets[j + 1] - offsets[j];
         if (n >= kMaxElements || offsets[j + 1] >= (1ull << 48)) return SHUF_EUNSUPPORTED;
         if (n >= 2) any = true;
-        arrays.push_back({offsets[j], n, static_cast<uint32_t>(j)});
     }
     if (!any) return SHUF_OK;
     if (!ptr) return SHUF_EINVAL;
@@ -529,7 +610,116 @@ int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t
     shuf_default_params(0, elem_bytes, &p);
     int rc = check_params(&p, elem_bytes);
     if (rc != SHUF_OK) return rc;
-    return run_locked(static_cast<uint8_t*>(ptr), elem_bytes, seed, p, arrays, stream);
+    Engine E = make_engine(elem_bytes, p);
+    const uint64_t base = reinterpret_cast<uintptr_t>(ptr) / elem_bytes;
+    for (uint64_t j = 0; j < count; ++j)
+        if (offsets[j + 1] - offsets[j] >= 2)
+            engine_submit(E, base + offsets[j], offsets[j + 1] - offsets[j], seed,
+                          static_cast<uint32_t>(j));
+    return engine_drain(E, stream);
+}
+
+static int check_array(const shuf_array_t& a, uint32_t w)
+{
+    if (a.n <= 1) return SHUF_OK;
+    if (!a.ptr) return SHUF_EINVAL;
+    if (reinterpret_cast<uintptr_t>(a.ptr) % w) return SHUF_EINVAL;
+    if (a.n >= kMaxElements) return SHUF_EUNSUPPORTED;
+    return SHUF_OK;
+}
+
+int shuffle_many(const shuf_array_t* arrays, uint64_t count, uint32_t elem_bytes, void* stream)
+{
+    if (!valid_width(elem_bytes) || (!arrays && count)) return SHUF_EINVAL;
+    if (count >= (1ull << 32)) return SHUF_EUNSUPPORTED;
+    for (uint64_t j = 0; j < count; ++j) {
+        const int rc = check_array(arrays[j], elem_bytes);
+        if (rc != SHUF_OK) return rc;
+    }
+    shuf_params_t p;
+    shuf_default_params(0, elem_bytes, &p);
+    Engine E = make_engine(elem_bytes, p);
+    for (uint64_t j = 0; j < count; ++j)
+        if (arrays[j].n >= 2)  // arrays of 0 or 1 element need no work
+            engine_submit(E, reinterpret_cast<uintptr_t>(arrays[j].ptr) / elem_bytes, arrays[j].n,
+                          arrays[j].seed, arrays[j].stream_id);
+    if (!E.inflight) return SHUF_OK;
+    return engine_drain(E, stream);
+}
+
+struct shuf_session {
+    int device;
+    Engine E;
+};
+
+int shuf_session_create(uint32_t elem_bytes, shuf_session_t** out)
+{
+    if (!out || !valid_width(elem_bytes)) return SHUF_EINVAL;
+    int dev = 0;
+    if (!current_context(&dev)) return SHUF_EHIP;
+    shuf_params_t p;
+    shuf_default_params(0, elem_bytes, &p);
+    shuf_session_t* s = new (std::nothrow) shuf_session_t{dev, make_engine(elem_bytes, p)};
+    if (!s) return SHUF_ENOMEM;
+    *out = s;
+    return SHUF_OK;
+}
+
+int shuf_session_submit(shuf_session_t* s, const shuf_array_t* a, uint64_t* ticket)
+{
+    if (!s || !a || !ticket) return SHUF_EINVAL;
+    if (s->E.broken) return SHUF_EHIP;
+    const int rc = check_array(*a, s->E.w);
+    if (rc != SHUF_OK) return rc;
+    if (s->E.ticket.size() >= (1ull << 31) && s->E.free_slots.empty()) return SHUF_EUNSUPPORTED;
+    *ticket = engine_submit(s->E, reinterpret_cast<uintptr_t>(a->ptr) / s->E.w, a->n, a->seed,
+                            a->stream_id);
+    return SHUF_OK;
+}
+
+int shuf_session_step(shuf_session_t* s, void* stream, uint64_t* done, uint64_t cap,
+                      uint64_t* ndone)
+{
+    if (!s || !ndone || (cap && !done)) return SHUF_EINVAL;
+    int dev = 0;
+    Context* C = current_context(&dev);
+    if (!C) return SHUF_EHIP;
+    if (dev != s->device) return SHUF_EINVAL;
+    if (s->E.inflight) {
+        std::lock_guard<std::mutex> lock(C->mu);
+        C->spans.clear();
+        C->events_used = 0;
+        shuf_stats_t st{};
+        const int rc = engine_step(*C, s->E, static_cast<hipStream_t>(stream), st);
+        if (rc != SHUF_OK) {
+            s->E.broken = true;
+            return rc;
+        }
+        C->stats = st;
+    }
+    const uint64_t k = std::min<uint64_t>(cap, s->E.done_queue.size());
+    for (uint64_t i = 0; i < k; ++i) done[i] = s->E.done_queue[i];
+    s->E.done_queue.erase(s->E.done_queue.begin(), s->E.done_queue.begin() + k);
+    *ndone = k;
+    return SHUF_OK;
+}
+
+int shuf_session_inflight(const shuf_session_t* s, uint64_t* inflight, uint64_t* completed_unread)
+{
+    if (!s || !inflight) return SHUF_EINVAL;
+    *inflight = s->E.inflight;
+    if (completed_unread) *completed_unread = s->E.done_queue.size();
+    return SHUF_OK;
+}
+
+int shuf_session_destroy(shuf_session_t* s)
+{
+    if (!s) return SHUF_EINVAL;
+    int dev = -1;
+    current_context(&dev);
+    if (dev == s->device) (void)hipDeviceSynchronize();
+    delete s;
+    return SHUF_OK;
 }
 
 const char* shuffle_strerror(int code)
@@ -546,10 +736,9 @@ const char* shuffle_strerror(int code)
 
 int shuffle_timing_enable(int on)
 {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return SHUF_EHIP;
-    if (dev < 0 || dev >= kMaxDevices) return SHUF_EUNSUPPORTED;
-    Context& C = g_ctx[dev];
+    Context* Cp = current_context();
+    if (!Cp) return SHUF_EHIP;
+    Context& C = *Cp;
     std::lock_guard<std::mutex> lock(C.mu);
     C.timing = on != 0;
     for (auto& t : C.times) t = shuf_kernel_time_t{};
@@ -561,10 +750,9 @@ int shuffle_timing_enable(int on)
 int shuffle_timing_read(shuf_kernel_time_t* out)
 {
     if (!out) return SHUF_EINVAL;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return SHUF_EHIP;
-    if (dev < 0 || dev >= kMaxDevices) return SHUF_EUNSUPPORTED;
-    Context& C = g_ctx[dev];
+    Context* Cp = current_context();
+    if (!Cp) return SHUF_EHIP;
+    Context& C = *Cp;
     std::lock_guard<std::mutex> lock(C.mu);
     for (int i = 0; i < SHUF_KERNEL_KINDS; ++i) out[i] = C.times[i];
     return SHUF_OK;
@@ -573,11 +761,10 @@ int shuffle_timing_read(shuf_kernel_time_t* out)
 int shuffle_last_stats(shuf_stats_t* out)
 {
     if (!out) return SHUF_EINVAL;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return SHUF_EHIP;
-    if (dev < 0 || dev >= kMaxDevices) return SHUF_EUNSUPPORTED;
-    std::lock_guard<std::mutex> lock(g_ctx[dev].mu);
-    *out = g_ctx[dev].stats;
+    Context* C = current_context();
+    if (!C) return SHUF_EHIP;
+    std::lock_guard<std::mutex> lock(C->mu);
+    *out = C->stats;
     return SHUF_OK;
 }
 

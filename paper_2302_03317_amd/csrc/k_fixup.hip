@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kTabThreads) void k_children(LevelTables T, uint32_
     const SubDesc sd = T.subs[T.bk_sub[gb]];
     const uint64_t n = T.N[gb];
     if (n <= 1) return;
-    const LeafDesc c{sd.elem_off, sd.base + T.S[gb], n, sd.level + 1, sd.stream_id};
+    const LeafDesc c{sd.elem_off, sd.base + T.S[gb], n, sd.seed, sd.level + 1, sd.stream_id, sd.owner, 0u};
     if (n <= tile_limit) {
         leaves[atomicAdd(&counters[0], 1ull)] = c;
         atomicAdd(&counters[2], static_cast<unsigned long long>(n));
@@ -258,8 +258,7 @@ __global__ __launch_bounds__(kTabThreads) void k_children(LevelTables T, uint32_
 
 // ---- gather: movers of one tile into the workspace ----
 template <typename E>
-__global__ __launch_bounds__(kTabThreads) void k_gather(uint8_t* __restrict__ buf,
-                                                        E* __restrict__ ws, LevelTables T)
+__global__ __launch_bounds__(kTabThreads) void k_gather(E* __restrict__ ws, LevelTables T)
 {
     __shared__ uint64_t lo[kKmax], kept_lo[kKmax], base_w[kKmax];
     __shared__ uint32_t fill[kKmax], kept[kKmax], disp[kKmax];
@@ -269,7 +268,7 @@ __global__ __launch_bounds__(kTabThreads) void k_gather(uint8_t* __restrict__ bu
     const SubDesc sd = T.subs[T.tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
     const uint32_t k = 1u << sd.kappa;
-    const E* X = reinterpret_cast<const E*>(buf) + sd.elem_off + sd.base;
+    const E* X = elem_ptr<E>(sd.elem_off) + sd.base;
     for (uint32_t b = tid; b < k; b += kTabThreads) {
         const uint64_t e = sd.tab_off + t * k + b;
         const uint64_t gb = sd.bk_off + b;
@@ -316,8 +315,7 @@ __global__ __launch_bounds__(kTabThreads) void k_gather(uint8_t* __restrict__ bu
 
 // ---- scatter: free slots of the tile's pieces from the workspace ----
 template <typename E>
-__global__ __launch_bounds__(kTabThreads) void k_scatter(uint8_t* __restrict__ buf,
-                                                         const E* __restrict__ ws, LevelTables T)
+__global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ ws, LevelTables T)
 {
     __shared__ uint64_t S[kKmax], Ktot[kKmax], MB[kKmax], lo[kKmax], kept_lo[kKmax], kpre[kKmax];
     __shared__ uint32_t kept[kKmax], nkt[kKmax + 1];
@@ -326,7 +324,7 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(uint8_t* __restrict__ b
     const SubDesc sd = T.subs[T.tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
     const uint32_t k = 1u << sd.kappa;
-    E* X = reinterpret_cast<E*>(buf) + sd.elem_off + sd.base;
+    E* X = elem_ptr<E>(sd.elem_off) + sd.base;
     for (uint32_t b = tid; b < k; b += kTabThreads) {
         const uint64_t e = sd.tab_off + t * k + b;
         const uint64_t gb = sd.bk_off + b;
@@ -413,42 +411,40 @@ hipError_t launch_children(const LevelTables& t, uint32_t tile_limit, LeafDesc* 
 }
 
 template <typename E>
-static hipError_t gather_t(uint8_t* buf, uint8_t* ws, const LevelTables& t, hipStream_t stream)
+static hipError_t gather_t(uint8_t* ws, const LevelTables& t, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_gather<E>, dim3(static_cast<uint32_t>(t.ntiles)), dim3(kTabThreads), 0,
-                       stream, buf, reinterpret_cast<E*>(ws), t);
+                       stream, reinterpret_cast<E*>(ws), t);
     return hipGetLastError();
 }
 
 template <typename E>
-static hipError_t scatter_t(uint8_t* buf, const uint8_t* ws, const LevelTables& t,
-                            hipStream_t stream)
+static hipError_t scatter_t(const uint8_t* ws, const LevelTables& t, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_scatter<E>, dim3(static_cast<uint32_t>(t.ntiles)), dim3(kTabThreads), 0,
-                       stream, buf, reinterpret_cast<const E*>(ws), t);
+                       stream, reinterpret_cast<const E*>(ws), t);
     return hipGetLastError();
 }
 
-hipError_t launch_gather(uint32_t w, uint8_t* buf, uint8_t* ws, const LevelTables& t,
-                         hipStream_t stream)
+hipError_t launch_gather(uint32_t w, uint8_t* ws, const LevelTables& t, hipStream_t stream)
 {
     if (t.ntiles == 0) return hipSuccess;
     switch (w) {
-    case 4: return gather_t<uint32_t>(buf, ws, t, stream);
-    case 8: return gather_t<uint64_t>(buf, ws, t, stream);
-    case 16: return gather_t<Elem16>(buf, ws, t, stream);
+    case 4: return gather_t<uint32_t>(ws, t, stream);
+    case 8: return gather_t<uint64_t>(ws, t, stream);
+    case 16: return gather_t<Elem16>(ws, t, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_scatter(uint32_t w, uint8_t* buf, const uint8_t* ws, const LevelTables& t,
+hipError_t launch_scatter(uint32_t w, const uint8_t* ws, const LevelTables& t,
                           hipStream_t stream)
 {
     if (t.ntiles == 0) return hipSuccess;
     switch (w) {
-    case 4: return scatter_t<uint32_t>(buf, ws, t, stream);
-    case 8: return scatter_t<uint64_t>(buf, ws, t, stream);
-    case 16: return scatter_t<Elem16>(buf, ws, t, stream);
+    case 4: return scatter_t<uint32_t>(ws, t, stream);
+    case 8: return scatter_t<uint64_t>(ws, t, stream);
+    case 16: return scatter_t<Elem16>(ws, t, stream);
     default: return hipErrorInvalidValue;
     }
 }

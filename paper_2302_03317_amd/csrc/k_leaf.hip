@@ -171,9 +171,8 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
 // One size class of leaves: at most kThreads * ROUNDS items each, LDS laid
 // out for the class capacity `cap`, MINW waves per SIMD.
 template <typename E, int ROUNDS, int MINW>
-__global__ __launch_bounds__(kThreads, MINW) void k_leaf(uint8_t* __restrict__ buf,
-                                                         const LeafDesc* __restrict__ leaves,
-                                                         uint64_t seed, Params prm, uint32_t cap)
+__global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restrict__ leaves,
+                                                         Params prm, uint32_t cap)
 {
     constexpr int EMAX = ROUNDS;
     constexpr uint32_t kWaveSegMax = 64u * ROUNDS;  // largest segment split by one wave
@@ -196,9 +195,9 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(uint8_t* __restrict__ b
     uint32_t* misc = reinterpret_cast<uint32_t*>(smem + LL.misc);
     E* stage = reinterpret_cast<E*>(smem);
 
-    E* X = reinterpret_cast<E*>(buf) + ld.elem_off + ld.base;
+    E* X = elem_ptr<E>(ld.elem_off) + ld.base;
     const uint64_t pbase = ld.base;
-    const Key key = make_key(seed, ld.stream_id);
+    const Key key = make_key(ld.seed, ld.stream_id);
     // labraw holds whole label blocks; lab[x] is the label byte of position pbase + x
     const uint8_t* lab = labraw + (pbase & 15);
 
@@ -355,13 +354,12 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(uint8_t* __restrict__ b
 }
 
 template <typename E>
-__global__ void k_fy_global(uint8_t* __restrict__ buf, const LeafDesc* __restrict__ items,
-                            uint64_t seed)
+__global__ void k_fy_global(const LeafDesc* __restrict__ items)
 {
     if (threadIdx.x != 0) return;
     const LeafDesc ld = items[blockIdx.x];
-    E* X = reinterpret_cast<E*>(buf) + ld.elem_off + ld.base;
-    const Key key = make_key(seed, ld.stream_id);
+    E* X = elem_ptr<E>(ld.elem_off) + ld.base;
+    const Key key = make_key(ld.seed, ld.stream_id);
     for (uint64_t i = ld.m - 1; i >= 1; --i) {
         const uint64_t p = ld.base + i;
         const uint32_t bound = static_cast<uint32_t>(i + 1);
@@ -389,29 +387,28 @@ struct LeafClasses {
 };
 
 template <typename E, int ROUNDS, int MINW>
-hipError_t leaf_class_t(uint8_t* buf, const LeafDesc* leaves, uint64_t n, uint64_t seed,
-                        const Params& prm, uint32_t cap, hipStream_t stream)
+hipError_t leaf_class_t(const LeafDesc* leaves, uint64_t n, const Params& prm, uint32_t cap,
+                        hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
     if (cap > static_cast<uint32_t>(ROUNDS) * kThreads) return hipErrorInvalidValue;
     const LeafLayout LL = leaf_layout(cap, sizeof(E), 1u << prm.kmax_log2, prm.n0);
     hipLaunchKernelGGL((k_leaf<E, ROUNDS, MINW>), dim3(static_cast<uint32_t>(n)), dim3(kThreads),
-                       LL.total, stream, buf, leaves, seed, prm, cap);
+                       LL.total, stream, leaves, prm, cap);
     return hipGetLastError();
 }
 
 template <typename E>
-hipError_t leaf_t(uint8_t* buf, const LeafDesc* leaves, const uint64_t* count, uint64_t stride,
-                  uint64_t seed, const Params& prm, const uint32_t* caps, hipStream_t stream)
+hipError_t leaf_t(const LeafDesc* leaves, const uint64_t* count, uint64_t stride, const Params& prm,
+                  const uint32_t* caps, hipStream_t stream)
 {
     using LC = LeafClasses<E>;
     hipError_t e;
-    e = leaf_class_t<E, LC::kRoundsS, 8>(buf, leaves, count[0], seed, prm, caps[0], stream);
+    e = leaf_class_t<E, LC::kRoundsS, 8>(leaves, count[0], prm, caps[0], stream);
     if (e != hipSuccess) return e;
-    e = leaf_class_t<E, LC::kRoundsM, 6>(buf, leaves + stride, count[1], seed, prm, caps[1], stream);
+    e = leaf_class_t<E, LC::kRoundsM, 6>(leaves + stride, count[1], prm, caps[1], stream);
     if (e != hipSuccess) return e;
-    return leaf_class_t<E, LC::kRoundsL, 4>(buf, leaves + 2 * stride, count[2], seed, prm, caps[2],
-                                            stream);
+    return leaf_class_t<E, LC::kRoundsL, 4>(leaves + 2 * stride, count[2], prm, caps[2], stream);
 }
 
 // Sort leaves into the three classes (order inside a class is immaterial:
@@ -428,10 +425,9 @@ __global__ void k_leaf_classes(const LeafDesc* __restrict__ in, uint64_t n,
 }
 
 template <typename E>
-hipError_t fy_t(uint8_t* buf, const LeafDesc* items, uint64_t n, uint64_t seed, hipStream_t stream)
+hipError_t fy_t(const LeafDesc* items, uint64_t n, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_fy_global<E>, dim3(static_cast<uint32_t>(n)), dim3(64), 0, stream, buf,
-                       items, seed);
+    hipLaunchKernelGGL(k_fy_global<E>, dim3(static_cast<uint32_t>(n)), dim3(64), 0, stream, items);
     return hipGetLastError();
 }
 
@@ -465,14 +461,13 @@ hipError_t launch_leaf_classes(const LeafDesc* in, uint64_t n, LeafDesc* out, ui
     return hipGetLastError();
 }
 
-hipError_t launch_leaf(uint32_t w, uint8_t* buf, const LeafDesc* leaves, const uint64_t* count,
-                       uint64_t stride, uint64_t seed, const Params& prm, const uint32_t* caps,
-                       hipStream_t stream)
+hipError_t launch_leaf(uint32_t w, const LeafDesc* leaves, const uint64_t* count, uint64_t stride,
+                       const Params& prm, const uint32_t* caps, hipStream_t stream)
 {
     switch (w) {
-    case 4: return leaf_t<uint32_t>(buf, leaves, count, stride, seed, prm, caps, stream);
-    case 8: return leaf_t<uint64_t>(buf, leaves, count, stride, seed, prm, caps, stream);
-    case 16: return leaf_t<Elem16>(buf, leaves, count, stride, seed, prm, caps, stream);
+    case 4: return leaf_t<uint32_t>(leaves, count, stride, prm, caps, stream);
+    case 8: return leaf_t<uint64_t>(leaves, count, stride, prm, caps, stream);
+    case 16: return leaf_t<Elem16>(leaves, count, stride, prm, caps, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -501,14 +496,13 @@ hipError_t set_leaf_lds_limits()
     return leaf_limits_t<Elem16>();
 }
 
-hipError_t launch_fy_global(uint32_t w, uint8_t* buf, const LeafDesc* items, uint64_t count,
-                            uint64_t seed, hipStream_t stream)
+hipError_t launch_fy_global(uint32_t w, const LeafDesc* items, uint64_t count, hipStream_t stream)
 {
     if (count == 0) return hipSuccess;
     switch (w) {
-    case 4: return fy_t<uint32_t>(buf, items, count, seed, stream);
-    case 8: return fy_t<uint64_t>(buf, items, count, seed, stream);
-    case 16: return fy_t<Elem16>(buf, items, count, seed, stream);
+    case 4: return fy_t<uint32_t>(items, count, stream);
+    case 8: return fy_t<uint64_t>(items, count, stream);
+    case 16: return fy_t<Elem16>(items, count, stream);
     default: return hipErrorInvalidValue;
     }
 }

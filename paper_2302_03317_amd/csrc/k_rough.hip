@@ -47,11 +47,9 @@ __device__ __forceinline__ void rank_rounds(const uint8_t* lab, uint32_t* Hw, ui
 }
 
 template <typename E, int R>
-__global__ __launch_bounds__(kThreads, 4) void k_rough(uint8_t* __restrict__ buf,
-                                                    const SubDesc* __restrict__ subs,
+__global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict__ subs,
                                                     const uint32_t* __restrict__ tile_sub,
-                                                    uint32_t* __restrict__ cnt_tab, uint64_t seed,
-                                                    Params prm)
+                                                    uint32_t* __restrict__ cnt_tab, Params prm)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
@@ -78,9 +76,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(uint8_t* __restrict__ buf
     uint32_t* hot = ovt + kmax + 1;
     uint32_t* nblk = hot + kmax + 1;
 
-    E* X = reinterpret_cast<E*>(buf) + sd.elem_off + sd.base;
+    E* X = elem_ptr<E>(sd.elem_off) + sd.base;
     const uint64_t pbase = sd.base;
-    const Key key = make_key(seed, sd.stream_id);
+    const Key key = make_key(sd.seed, sd.stream_id);
 
     // Pieces of this tile, their offsets in read order, and the label blocks
     // (16 positions per Philox call) each piece touches.
@@ -273,28 +271,26 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(uint8_t* __restrict__ buf
 }
 
 template <typename E>
-hipError_t launch_rough_t(uint8_t* buf, const SubDesc* subs, const uint32_t* tile_sub,
-                          uint32_t* cnt_tab, uint64_t ntiles, uint64_t seed, const Params& prm,
-                          hipStream_t stream)
+hipError_t launch_rough_t(const SubDesc* subs, const uint32_t* tile_sub, uint32_t* cnt_tab,
+                          uint64_t ntiles, const Params& prm, hipStream_t stream)
 {
     constexpr int R = static_cast<int>(kTileBytesMax / (sizeof(E) * kThreads));
     const RoughLayout L = rough_layout(prm.tile, sizeof(E), 1u << prm.kmax_log2);
     if (ntiles == 0) return hipSuccess;
     hipLaunchKernelGGL((k_rough<E, R>), dim3(static_cast<uint32_t>(ntiles)), dim3(kThreads),
-                       L.total, stream, buf, subs, tile_sub, cnt_tab, seed, prm);
+                       L.total, stream, subs, tile_sub, cnt_tab, prm);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_rough(uint32_t w, uint8_t* buf, const SubDesc* subs, const uint32_t* tile_sub,
-                        uint32_t* cnt_tab, uint64_t ntiles, uint64_t seed, const Params& prm,
-                        hipStream_t stream)
+hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_sub,
+                        uint32_t* cnt_tab, uint64_t ntiles, const Params& prm, hipStream_t stream)
 {
     switch (w) {
-    case 4: return launch_rough_t<uint32_t>(buf, subs, tile_sub, cnt_tab, ntiles, seed, prm, stream);
-    case 8: return launch_rough_t<uint64_t>(buf, subs, tile_sub, cnt_tab, ntiles, seed, prm, stream);
-    case 16: return launch_rough_t<Elem16>(buf, subs, tile_sub, cnt_tab, ntiles, seed, prm, stream);
+    case 4: return launch_rough_t<uint32_t>(subs, tile_sub, cnt_tab, ntiles, prm, stream);
+    case 8: return launch_rough_t<uint64_t>(subs, tile_sub, cnt_tab, ntiles, prm, stream);
+    case 16: return launch_rough_t<Elem16>(subs, tile_sub, cnt_tab, ntiles, prm, stream);
     default: return hipErrorInvalidValue;
     }
 }

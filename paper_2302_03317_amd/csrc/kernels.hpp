@@ -12,10 +12,12 @@ struct __attribute__((aligned(16))) Elem16 {
     uint64_t lo, hi;
 };
 
+// Every kernel addresses elements through the descriptors' element
+// addresses (see elem_ptr) and keys its randomness with their seeds.
+
 // Rough pass of one tiled level: one workgroup per tile.
-hipError_t launch_rough(uint32_t w, uint8_t* buf, const SubDesc* subs, const uint32_t* tile_sub,
-                        uint32_t* cnt_tab, uint64_t ntiles, uint64_t seed, const Params& prm,
-                        hipStream_t stream);
+hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_sub,
+                        uint32_t* cnt_tab, uint64_t ntiles, const Params& prm, hipStream_t stream);
 hipError_t set_rough_lds_limits();
 
 // Device tables of one tiled level (see k_fixup.hip).
@@ -54,9 +56,8 @@ hipError_t launch_children(const LevelTables& t, uint32_t tile_limit, LeafDesc* 
 hipError_t launch_tables_sizes(const LevelTables& t, hipStream_t stream);
 hipError_t launch_tables_routes(const LevelTables& t, hipStream_t stream);
 // Fix-up: gather movers into the workspace, then scatter into free slots.
-hipError_t launch_gather(uint32_t w, uint8_t* buf, uint8_t* ws, const LevelTables& t,
-                         hipStream_t stream);
-hipError_t launch_scatter(uint32_t w, uint8_t* buf, const uint8_t* ws, const LevelTables& t,
+hipError_t launch_gather(uint32_t w, uint8_t* ws, const LevelTables& t, hipStream_t stream);
+hipError_t launch_scatter(uint32_t w, const uint8_t* ws, const LevelTables& t,
                           hipStream_t stream);
 
 // Subproblems that fit a tile: in-LDS levels and Fisher-Yates, launched per
@@ -65,13 +66,11 @@ void leaf_class_caps(uint32_t w, const Params& prm, uint32_t* caps);
 hipError_t launch_leaf_classes(const LeafDesc* in, uint64_t n, LeafDesc* out, uint64_t stride,
                                const uint32_t* caps, unsigned long long* count, hipStream_t stream);
 // leaves of class c are leaves[c * stride, c * stride + count[c])
-hipError_t launch_leaf(uint32_t w, uint8_t* buf, const LeafDesc* leaves, const uint64_t* count,
-                       uint64_t stride, uint64_t seed, const Params& prm, const uint32_t* caps,
-                       hipStream_t stream);
+hipError_t launch_leaf(uint32_t w, const LeafDesc* leaves, const uint64_t* count, uint64_t stride,
+                       const Params& prm, const uint32_t* caps, hipStream_t stream);
 hipError_t set_leaf_lds_limits();
 // Sequential Fisher-Yates in global memory (recursion cap reached on a
 // subproblem that does not fit a tile).
-hipError_t launch_fy_global(uint32_t w, uint8_t* buf, const LeafDesc* items, uint64_t count,
-                            uint64_t seed, hipStream_t stream);
+hipError_t launch_fy_global(uint32_t w, const LeafDesc* items, uint64_t count, hipStream_t stream);
 
 }  // namespace ipss

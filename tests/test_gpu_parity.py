@@ -207,3 +207,80 @@ def test_argument_errors_leave_data_untouched():
     # n <= 1 is a successful no-op, even with a NULL pointer
     assert shuf.raw_call("shuffle_inplace", null, 1, 4, 1, null) == 0
     assert shuf.raw_call("shuffle_inplace", null, 0, 8, 1, null) == 0
+
+
+def test_many_arrays_in_separate_allocations():
+    """shuffle_many: arrays anywhere in device memory, each with its own seed
+    and stream id, equal the single-array definition."""
+    shuf = _lib()
+    rng = np.random.default_rng(11)
+    sizes = [0, 1, 2, 63, 64, 65, 1000, 16127, 16128, 16129, 40000, 300000]
+    for w in (4, 8, 16):
+        hosts = [workloads.random_values(n, w, 100 + i) for i, n in enumerate(sizes)]
+        seeds = [int(rng.integers(0, 2**63)) for _ in sizes]
+        sids = [int(rng.integers(0, 2**32)) for _ in sizes]
+        tens = [to_dev(h) for h in hosts]
+        print(f"[gpu] shuffle_many w={w} arrays={len(sizes)}", flush=True)
+        shuf.shuffle_many(tens, seeds, sids)
+        torch.cuda.synchronize()
+        for h, t, sd, sid in zip(hosts, tens, seeds, sids):
+            want = oracle_shuffle(h, sd, oracle.default_params(h.shape[0], w), stream_id=sid)
+            assert_same(from_dev(t, h), want, f"many w={w} n={h.shape[0]}")
+
+
+def test_batched_equals_many():
+    shuf = _lib()
+    sizes = workloads.log_uniform_sizes(200, 4, 18, seed=9)
+    offs = workloads.csr_offsets(sizes)
+    host = workloads.batched_identity(sizes)
+    a = to_dev(host)
+    print(f"[gpu] batched vs many: arrays={len(sizes)} total={host.size}", flush=True)
+    shuf.shuffle_batched(a, offs, 4242)
+    b = to_dev(host)
+    views = [b[int(offs[j]):int(offs[j + 1])] for j in range(len(sizes))]
+    shuf.shuffle_many(views, [4242] * len(sizes), list(range(len(sizes))))
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev(a, host), from_dev(b, host))
+
+
+def test_session_result_same_alone_and_in_mix():
+    """Continuous batching: requests join while others are in flight; every
+    result equals the same request run alone (the oracle, and the GPU
+    single-array call)."""
+    shuf = _lib()
+    w = 8
+    rng = np.random.default_rng(5)
+    plan = []  # (step at which it is submitted, n)
+    for step in range(6):
+        for _ in range(3):
+            plan.append((step, int(2 ** rng.uniform(10, 21))))
+    plan.append((0, 1))
+    plan.append((2, 0))
+    reqs = []
+    with shuf.Session(w) as sess:
+        step = 0
+        pending = list(plan)
+        done = set()
+        while pending or sess.inflight()[0]:
+            for item in [p for p in pending if p[0] == step]:
+                n = item[1]
+                h = workloads.random_values(n, w, 1000 + len(reqs))
+                t = to_dev(h)
+                seed = int(rng.integers(0, 2**64, dtype=np.uint64))
+                sid = int(rng.integers(0, 2**32))
+                tk = sess.submit(t, seed, sid)
+                reqs.append((tk, h, t, seed, sid, step))
+                pending.remove(item)
+            print(f"[gpu] session step {step} inflight={sess.inflight()}", flush=True)
+            done.update(sess.step())
+            step += 1
+            assert step < 100
+        torch.cuda.synchronize()
+    assert done == {r[0] for r in reqs}
+    for tk, h, t, seed, sid, st in reqs:
+        want = oracle_shuffle(h, seed, oracle.default_params(h.shape[0], w), stream_id=sid)
+        assert_same(from_dev(t, h), want, f"session request {tk} n={h.shape[0]} submitted at step {st}")
+        alone = to_dev(h)
+        shuf.shuffle_inplace_ex(alone, seed, sid)
+        torch.cuda.synchronize()
+        assert_same(from_dev(alone, h), want, f"alone {tk}")

@@ -65,3 +65,28 @@ def test_invalid_arguments_rejected_without_gpu():
     assert shuf.raw_call("shuffle_inplace_ex", null, 10, 4, 1, 0, ctypes.byref(p), null) == shuf.SHUF_EINVAL
     offs = (ctypes.c_uint64 * 3)(0, 5, 4)
     assert shuf.raw_call("shuffle_batched", null, offs, 2, 4, 1, null) == shuf.SHUF_EINVAL
+
+
+def test_multi_array_and_session_argument_checks_without_gpu():
+    """shuffle_many and the session calls validate arguments before any HIP call."""
+    shuf = _lib()
+    lib = shuf.lib()
+    null = ctypes.c_void_p(0)
+    assert lib.shuffle_many(None, 3, 4, null) == shuf.SHUF_EINVAL
+    assert lib.shuffle_many(None, 0, 5, null) == shuf.SHUF_EINVAL
+    bad = (shuf._Array * 2)(shuf._Array(None, 10, 1, 0, 0), shuf._Array(None, 1, 1, 1, 0))
+    assert lib.shuffle_many(bad, 2, 4, null) == shuf.SHUF_EINVAL       # NULL ptr with n > 1
+    odd = (shuf._Array * 1)(shuf._Array(ctypes.c_void_p(0x1002), 10, 1, 0, 0))
+    assert lib.shuffle_many(odd, 1, 4, null) == shuf.SHUF_EINVAL       # misaligned
+    big = (shuf._Array * 1)(shuf._Array(ctypes.c_void_p(0x1000), 1 << 41, 1, 0, 0))
+    assert lib.shuffle_many(big, 1, 4, null) == shuf.SHUF_EUNSUPPORTED
+    trivial = (shuf._Array * 2)(shuf._Array(None, 0, 1, 0, 0), shuf._Array(None, 1, 1, 1, 0))
+    assert lib.shuffle_many(trivial, 2, 8, null) == 0                  # nothing to do
+    t = ctypes.c_uint64()
+    a = shuf._Array(null, 10, 1, 0, 0)
+    assert lib.shuf_session_submit(None, ctypes.byref(a), ctypes.byref(t)) == shuf.SHUF_EINVAL
+    nd = ctypes.c_uint64()
+    assert lib.shuf_session_step(None, null, None, 0, ctypes.byref(nd)) == shuf.SHUF_EINVAL
+    assert lib.shuf_session_inflight(None, ctypes.byref(nd), None) == shuf.SHUF_EINVAL
+    assert lib.shuf_session_create(3, None) == shuf.SHUF_EINVAL
+    assert lib.shuf_session_destroy(None) == shuf.SHUF_EINVAL
