@@ -8,6 +8,14 @@ resident in HBM.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--config NAME]
 
+The default line also carries a "batched" object: 10,000 ragged u32 arrays
+(sizes floor(2^(4 + 16U))) shuffled by one shuffle_batched call, against a
+loop of per-array shuffle_inplace_ex calls on the same data (same bytes out).
+--config serve_u64 runs the serving workload instead: a Poisson stream of
+u64 requests (sizes log-uniform in [2^10, 2^26]) admitted under a 64 GiB HBM
+budget into a continuous-batching session, against serving the same stream
+one request at a time; p50/p99 latency and Gelem/s per arrival rate.
+
 Per-kernel times come from HIP events that the library records on the
 launch stream around every kernel group inside the timed region.  The CPU
 baseline times the CPU oracle on a bounded sample on the host.
@@ -88,12 +96,165 @@ def cpu_baseline(log2n: int, w: int) -> dict:
     }
 
 
+def cpu_fisher_yates(log2n: int, w: int) -> dict:
+    """Textbook sequential Fisher-Yates (the oracle's draws) on one host core."""
+    import oracle
+    import workloads
+
+    n = 1 << log2n
+    a = workloads.identity(n, w)
+    t0 = time.perf_counter()
+    oracle.fisher_yates(a, 0x5EED)
+    dt = time.perf_counter() - t0
+    return {
+        "value": n / dt / 1e9,
+        "unit": "Gelem/s",
+        "cores": 1,
+        "kind": "sequential Fisher-Yates",
+        "sample": f"2^{log2n} {w}-byte identity elements, {dt:.1f} s on one host core",
+    }
+
+
+def batched_compare(torch, shuf, count: int = 10000, seed: int = 2026) -> dict:
+    """shuffle_batched on `count` ragged u32 arrays vs per-array launches."""
+    import numpy as np
+
+    import workloads
+
+    sizes = workloads.log_uniform_sizes(count, 4, 20, seed=seed)
+    offs = workloads.csr_offsets(sizes)
+    host = workloads.batched_identity(sizes)
+    total = int(host.size)
+    a = torch.from_numpy(host.view(np.int32)).to("cuda:0")
+    b = a.clone()
+    views = [b[int(offs[j]):int(offs[j + 1])] for j in range(count)]
+    s0 = int.from_bytes(os.urandom(8), "little")
+    shuf.shuffle_batched(a, offs, s0)          # warm-up (pools, first launches)
+    for j, v in enumerate(views):
+        if v.shape[0] > 1:
+            shuf.shuffle_inplace_ex(v, s0, j)
+    torch.cuda.synchronize()
+    seed_t = int.from_bytes(os.urandom(8), "little")
+    reps = 5
+    t0 = time.perf_counter()
+    for r in range(reps):
+        shuf.shuffle_batched(a, offs, seed_t + r)
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for r in range(reps):
+        for j, v in enumerate(views):
+            if v.shape[0] > 1:
+                shuf.shuffle_inplace_ex(v, seed_t + r, j)
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / reps
+    same = bool(torch.equal(a, b))
+    return {
+        "workload": f"{count} u32 arrays, sizes floor(2^(4+16U)), {total} elements "
+                    f"({total * 4 / 2**30:.2f} GiB), identity per array, sizes seed {seed}",
+        "batched_ms": t_batched * 1e3,
+        "batched_Gelem_s": total / t_batched / 1e9,
+        "per_array_launches_ms": t_single * 1e3,
+        "per_array_Gelem_s": total / t_single / 1e9,
+        "speedup": t_single / t_batched,
+        "identical_outputs": same,
+    }
+
+
+def serving(torch, shuf, rates, count: int, budget_bytes: int, seed: int = 7) -> list:
+    """Poisson stream of u64 shuffle requests; continuous batching vs one at a time."""
+    import numpy as np
+
+    import workloads
+
+    w = 8
+    sizes = workloads.log_uniform_sizes(count, 10, 26, seed=seed)
+    charge = [int(n) * w * 115 // 100 for n in sizes]  # data plus a workspace allowance
+    # request data stays resident: one buffer per request size class, reused
+    bufs = [torch.empty(int(n), dtype=torch.int64, device="cuda:0") for n in sizes]
+    # warm-up: grow the library's pools with a burst of the largest requests
+    big = sorted(range(count), key=lambda j: -int(sizes[j]))[:64]
+    with shuf.Session(w) as sess:
+        for j in big:
+            sess.submit(bufs[j], j, j)
+        while sess.inflight()[0]:
+            sess.step()
+    for j in big[:8]:
+        shuf.shuffle_inplace_ex(bufs[j], j, j)
+    torch.cuda.synchronize()
+    results = []
+    for rate in rates:
+        arrivals = workloads.poisson_arrivals(count, rate, seed + int(rate))
+        seeds = np.random.default_rng(seed + 1).integers(0, 2**63, size=count)
+        for mode in ("session", "one_at_a_time"):
+            lat = np.zeros(count)
+            steps = 0
+            batch = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "session":
+                sess = shuf.Session(w)
+                nxt, used, submitted = 0, 0, {}
+                done_n = 0
+                while done_n < count:
+                    now = time.perf_counter() - t0
+                    while nxt < count and arrivals[nxt] <= now and used + charge[nxt] <= budget_bytes:
+                        tk = sess.submit(bufs[nxt], int(seeds[nxt]), nxt)
+                        submitted[tk] = nxt
+                        used += charge[nxt]
+                        nxt += 1
+                    inflight = sess.inflight()[0]
+                    if inflight == 0:
+                        if nxt < count:
+                            wait = arrivals[nxt] - (time.perf_counter() - t0)
+                            if wait > 0:
+                                time.sleep(min(wait, 0.001))
+                        continue
+                    batch.append(inflight)
+                    done = sess.step()
+                    steps += 1
+                    tdone = time.perf_counter() - t0
+                    for tk in done:
+                        j = submitted.pop(tk)
+                        lat[j] = tdone - arrivals[j]
+                        used -= charge[j]
+                        done_n += 1
+                sess.close()
+            else:
+                for j in range(count):
+                    now = time.perf_counter() - t0
+                    if arrivals[j] > now:
+                        time.sleep(arrivals[j] - now)
+                    shuf.shuffle_inplace_ex(bufs[j], int(seeds[j]), j)
+                    lat[j] = time.perf_counter() - t0 - arrivals[j]
+            elapsed = time.perf_counter() - t0
+            elems = float(np.sum(sizes))
+            results.append({
+                "rate_per_s": rate,
+                "mode": mode,
+                "requests": count,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "Gelem_s": elems / elapsed / 1e9,
+                "elapsed_s": elapsed,
+                "steps": steps,
+                "mean_inflight_per_step": float(np.mean(batch)) if batch else None,
+            })
+            print(f"[serve] rate {rate}/s {mode}: p50 {results[-1]['p50_ms']:.2f} ms "
+                  f"p99 {results[-1]['p99_ms']:.2f} ms {results[-1]['Gelem_s']:.2f} Gelem/s",
+                  file=sys.stderr, flush=True)
+    return results
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="u32_2e32", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="u32_2e32", choices=sorted(CONFIGS) + ["serve_u64"])
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-rates", default="1000,2000,4000,8000,16000")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -105,6 +266,24 @@ def main() -> int:
     import torch
 
     import paper_2302_03317_amd as shuf
+
+    if args.config == "serve_u64":
+        rates = [float(r) for r in args.serve_rates.split(",")]
+        res = serving(torch, shuf, rates, args.serve_requests, 64 << 30)
+        top = [r for r in res if r["mode"] == "session"][-1]
+        print(json.dumps({
+            "metric": "serving: p50/p99 latency and Gelem/s under Poisson arrivals",
+            "value": top["Gelem_s"], "unit": "Gelem/s", "n_gpus": 1,
+            "steps": args.serve_requests, "warmup": 0,
+            "ms_per_step": top["elapsed_s"] * 1e3 / args.serve_requests,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+            "data": "synthetic",
+            "config": {"workload": "Poisson stream of in-place shuffles of u64 arrays, sizes "
+                                   "log-uniform in [2^10, 2^26], 64 GiB HBM budget, data resident",
+                       "rates_per_s": rates, "requests_per_rate": args.serve_requests},
+            "sweep": res,
+        }), flush=True)
+        return 0
 
     log2n, w, desc = CONFIGS[args.config]
     n = 1 << log2n
@@ -195,8 +374,13 @@ def main() -> int:
                    "leaves_last_step": stats["leaves"], "workspace_bytes": stats["workspace_bytes"]},
         "checksum_preserved": before == after,
     }
+    if not args.no_batched:
+        del t
+        torch.cuda.empty_cache()
+        line["batched"] = batched_compare(torch, shuf)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(min(args.cpu_sample_log2, log2n), w)
+        line["cpu_fisher_yates"] = cpu_fisher_yates(min(args.cpu_sample_log2, log2n), w)
     print(json.dumps(line), flush=True)
     return 0 if before == after else 1
 

@@ -74,3 +74,9 @@ def batched_identity(sizes: np.ndarray) -> np.ndarray:
         out[pos:pos + s] = np.arange(s, dtype=np.uint32)
         pos += int(s)
     return out
+
+
+def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of `rate` per second."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
