@@ -55,7 +55,7 @@ def fill_identity(t, n, w, torch):
             t[a:b] = idx
         else:
             t[a:b, 0] = idx
-            z = idx + 0x9E3779B97F4A7C15 - (1 << 64)  # splitmix64(i), wrapping int64 arithmetic
+            z = idx + (0x9E3779B97F4A7C15 - (1 << 64))  # splitmix64(i), wrapping int64 arithmetic
             z = (z ^ (z >> 30).bitwise_and((1 << 34) - 1)) * (0xBF58476D1CE4E5B9 - (1 << 64))
             z = (z ^ (z >> 27).bitwise_and((1 << 37) - 1)) * (0x94D049BB133111EB - (1 << 64))
             t[a:b, 1] = z ^ (z >> 31).bitwise_and((1 << 33) - 1)

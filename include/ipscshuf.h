@@ -142,8 +142,9 @@ int shuffle_many(const shuf_array_t* arrays, uint64_t count, uint32_t elem_bytes
  *                         completions are reported by later calls
  *   shuf_session_inflight requests submitted and not yet complete, and
  *                         completed tickets not yet reported (may be NULL)
- *   shuf_session_destroy  waits for the device and frees the session (requests
- *                         still in flight are abandoned, their data unspecified)
+ *   shuf_session_destroy  waits for the session's device and frees the session
+ *                         and its device memory (requests still in flight are
+ *                         abandoned, their data unspecified)
  * A session is used by one host thread at a time; steps of sessions and other
  * calls on one device are serialised by the library.  After a step fails with
  * SHUF_EHIP the session only returns SHUF_EHIP.  Errors otherwise as above. */

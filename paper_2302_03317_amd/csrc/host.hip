@@ -29,6 +29,12 @@ constexpr uint64_t kMaxElements = 1ull << 40;
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
     hipError_t ensure(size_t bytes)
     {
         if (bytes <= cap && p) return hipSuccess;
@@ -80,6 +86,12 @@ hipError_t grow_keep(DevBuf& d, size_t bytes, size_t used, hipStream_t s)
 struct HostBuf {
     void* p = nullptr;
     size_t cap = 0;
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
     hipError_t ensure(size_t bytes)
     {
         if (bytes <= cap && p) return hipSuccess;
@@ -100,8 +112,22 @@ struct HostBuf {
     template <typename T> T* as() { return static_cast<T*>(p); }
 };
 
+// Device leaf lists of an engine: leaves[which] holds the leaves of the next
+// step, the other receives the children of the current one.
+struct LeafLists {
+    DevBuf leaves[2];
+    HostBuf h_new;  // staging of newly submitted leaves
+    void release()
+    {
+        leaves[0].release();
+        leaves[1].release();
+        h_new.release();
+    }
+};
+
 struct Context {
     std::mutex mu;
+    LeafLists lists;  // used by blocking calls (under mu)
     bool init = false;
     DevBuf subs, tile_sub, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, wsp, total, ws,
         leaves, leaves_cls, big, gfy, err, counters;
@@ -241,8 +267,7 @@ struct Engine {
     Params prm{};
     std::vector<HostSub> cur;          // tiled subproblems (and fallback items) of the next step
     std::vector<LeafDesc> new_leaves;  // leaves of newly submitted arrays
-    DevBuf leaves[2];                  // leaf lists: leaves[which] holds those of the next step
-    HostBuf h_new;
+    LeafLists* lists = nullptr;        // device leaf lists (the context's or a session's)
     int which = 0;
     uint64_t nleaves = 0, leaf_elems = 0;
     std::vector<uint64_t> ticket;  // owner slot -> ticket (0 = free)
@@ -304,18 +329,18 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     // Leaves of newly submitted arrays join this step's leaf list.
     if (!E.new_leaves.empty()) {
         const size_t add = E.new_leaves.size() * sizeof(LeafDesc);
-        DevBuf& L = E.leaves[E.which];
+        DevBuf& L = E.lists->leaves[E.which];
         HIP_TRY(grow_keep(L, E.nleaves * sizeof(LeafDesc) + add, E.nleaves * sizeof(LeafDesc), stream));
-        HIP_TRY(E.h_new.ensure(add));
-        std::memcpy(E.h_new.p, E.new_leaves.data(), add);
-        HIP_TRY(hipMemcpyAsync(static_cast<uint8_t*>(L.p) + E.nleaves * sizeof(LeafDesc), E.h_new.p,
-                               add, hipMemcpyHostToDevice, stream));
+        HIP_TRY(E.lists->h_new.ensure(add));
+        std::memcpy(E.lists->h_new.p, E.new_leaves.data(), add);
+        HIP_TRY(hipMemcpyAsync(static_cast<uint8_t*>(L.p) + E.nleaves * sizeof(LeafDesc),
+                               E.lists->h_new.p, add, hipMemcpyHostToDevice, stream));
         for (const LeafDesc& l : E.new_leaves) E.leaf_elems += l.m;
         E.nleaves += E.new_leaves.size();
         E.new_leaves.clear();
     }
     const uint64_t run_leaves = E.nleaves, run_leaf_elems = E.leaf_elems;
-    const LeafDesc* leaves_now = static_cast<const LeafDesc*>(E.leaves[E.which].p);
+    const LeafDesc* leaves_now = static_cast<const LeafDesc*>(E.lists->leaves[E.which].p);
     uint32_t caps[3];
     leaf_class_caps(w, prm, caps);
     if (run_leaves) {
@@ -400,7 +425,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
         HIP_TRY(C.K.ensure(nbk * 8));
         HIP_TRY(C.MB.ensure(nbk * 8));
         HIP_TRY(C.wsp.ensure((nbk / kScanChunk + 2) * 8));
-        HIP_TRY(E.leaves[1 - E.which].ensure(nbk * sizeof(LeafDesc)));
+        HIP_TRY(E.lists->leaves[1 - E.which].ensure(nbk * sizeof(LeafDesc)));
         HIP_TRY(C.big.ensure(nbk * sizeof(LeafDesc)));
 
         T.subs = static_cast<const SubDesc*>(C.subs.p);
@@ -433,7 +458,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
             HIP_TRY(launch_tables_sizes(T, stream));
             HIP_TRY(launch_tables_routes(T, stream));
             HIP_TRY(launch_children(T, static_cast<uint32_t>(tile_limit),
-                                    static_cast<LeafDesc*>(E.leaves[1 - E.which].p),
+                                    static_cast<LeafDesc*>(E.lists->leaves[1 - E.which].p),
                                     static_cast<LeafDesc*>(C.big.p), dc, stream));
         }
         HIP_TRY(hipMemcpyAsync(C.h_total.p, T.total, 8, hipMemcpyDeviceToHost, stream));
@@ -531,6 +556,7 @@ int engine_drain(Engine& E, void* stream)
     std::lock_guard<std::mutex> lock(C->mu);
     C->spans.clear();
     C->events_used = 0;
+    E.lists = &C->lists;
     shuf_stats_t st{};
     while (E.inflight) {
         const int rc = engine_step(*C, E, static_cast<hipStream_t>(stream), st);
@@ -650,6 +676,7 @@ int shuffle_many(const shuf_array_t* arrays, uint64_t count, uint32_t elem_bytes
 struct shuf_session {
     int device;
     Engine E;
+    LeafLists lists;
 };
 
 int shuf_session_create(uint32_t elem_bytes, shuf_session_t** out)
@@ -659,8 +686,9 @@ int shuf_session_create(uint32_t elem_bytes, shuf_session_t** out)
     if (!current_context(&dev)) return SHUF_EHIP;
     shuf_params_t p;
     shuf_default_params(0, elem_bytes, &p);
-    shuf_session_t* s = new (std::nothrow) shuf_session_t{dev, make_engine(elem_bytes, p)};
+    shuf_session_t* s = new (std::nothrow) shuf_session_t{dev, make_engine(elem_bytes, p), {}};
     if (!s) return SHUF_ENOMEM;
+    s->E.lists = &s->lists;
     *out = s;
     return SHUF_OK;
 }
@@ -716,8 +744,11 @@ int shuf_session_destroy(shuf_session_t* s)
 {
     if (!s) return SHUF_EINVAL;
     int dev = -1;
-    current_context(&dev);
-    if (dev == s->device) (void)hipDeviceSynchronize();
+    const bool have = current_context(&dev) != nullptr;
+    if (have && dev != s->device) (void)hipSetDevice(s->device);
+    (void)hipDeviceSynchronize();
+    s->lists.release();
+    if (have && dev != s->device) (void)hipSetDevice(dev);
     delete s;
     return SHUF_OK;
 }

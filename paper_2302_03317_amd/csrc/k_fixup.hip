@@ -242,18 +242,26 @@ __global__ __launch_bounds__(kTabThreads) void k_children(LevelTables T, uint32_
                                                           LeafDesc* leaves, LeafDesc* big,
                                                           unsigned long long* counters)
 {
+    // No early exit: every lane takes part in the wave-wide slot reservations.
     const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * kTabThreads + threadIdx.x;
-    if (gb >= T.nbuckets) return;
-    const SubDesc sd = T.subs[T.bk_sub[gb]];
-    const uint64_t n = T.N[gb];
-    if (n <= 1) return;
-    const LeafDesc c{sd.elem_off, sd.base + T.S[gb], n, sd.seed, sd.level + 1, sd.stream_id, sd.owner, 0u};
-    if (n <= tile_limit) {
-        leaves[atomicAdd(&counters[0], 1ull)] = c;
-        atomicAdd(&counters[2], static_cast<unsigned long long>(n));
-    } else {
-        big[atomicAdd(&counters[1], 1ull)] = c;
+    uint64_t n = 0;
+    LeafDesc c{};
+    if (gb < T.nbuckets) {
+        const SubDesc sd = T.subs[T.bk_sub[gb]];
+        n = T.N[gb];
+        c = LeafDesc{sd.elem_off, sd.base + T.S[gb], n, sd.seed, sd.level + 1, sd.stream_id,
+                     sd.owner, 0u};
     }
+    const bool leaf = n >= 2 && n <= tile_limit;
+    const bool more = n > tile_limit;
+    const uint64_t li = wave_reserve(&counters[0], leaf);
+    if (leaf) leaves[li] = c;
+    const uint64_t bi = wave_reserve(&counters[1], more);
+    if (more) big[bi] = c;
+    // leaf children hold at most tile_limit < 2^16 items: the wave's sum fits 32 bits
+    const uint32_t sum = wave_inclusive_sum(leaf ? static_cast<uint32_t>(n) : 0u);
+    const uint32_t total = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(sum), 63));
+    if (lane_id() == 0 && total) atomicAdd(&counters[2], static_cast<unsigned long long>(total));
 }
 
 // ---- gather: movers of one tile into the workspace ----

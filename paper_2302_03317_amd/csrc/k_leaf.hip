@@ -413,15 +413,23 @@ hipError_t leaf_t(const LeafDesc* leaves, const uint64_t* count, uint64_t stride
 
 // Sort leaves into the three classes (order inside a class is immaterial:
 // every leaf is finished independently).
-__global__ void k_leaf_classes(const LeafDesc* __restrict__ in, uint64_t n,
-                               LeafDesc* __restrict__ out, uint64_t stride, uint32_t cap_s,
-                               uint32_t cap_m, unsigned long long* __restrict__ count)
+__global__ __launch_bounds__(256) void k_leaf_classes(const LeafDesc* __restrict__ in, uint64_t n,
+                                                       LeafDesc* __restrict__ out, uint64_t stride,
+                                                       uint32_t cap_s, uint32_t cap_m,
+                                                       unsigned long long* __restrict__ count)
 {
+    // No early exit: every lane takes part in the wave-wide slot reservations.
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const LeafDesc d = in[i];
-    const uint32_t c = d.m <= cap_s ? 0u : (d.m <= cap_m ? 1u : 2u);
-    out[c * stride + atomicAdd(&count[c], 1ull)] = d;
+    LeafDesc d{};
+    uint32_t c = 3;
+    if (i < n) {
+        d = in[i];
+        c = d.m <= cap_s ? 0u : (d.m <= cap_m ? 1u : 2u);
+    }
+    for (uint32_t k = 0; k < 3; ++k) {
+        const uint64_t slot = wave_reserve(&count[k], c == k);
+        if (c == k) out[k * stride + slot] = d;
+    }
 }
 
 template <typename E>
