@@ -42,6 +42,35 @@ CONFIGS = {
 }
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of a kernel, from two rocprofv3 counter runs of this
+# benchmark (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by
+# what the same counter read for a plain 16 GiB device copy in the same run
+# (see profiles/traffic_k_rough_u32_2e32.md).  Valid only for the kernel
+# sources they were taken on: a different source hash reports null.
+TRAFFIC = {
+    ("u32_2e32", "rough"): {
+        "read_bytes": 20.436e9,
+        "write_bytes": 18.009e9,
+        "sources": ["k_rough.hip", "common.hpp", "rng.hpp", "kernels.hpp"],
+        "sha256": "40ccfc94baad81baa50994c018a6ff468f1182b49111fd0dde7808b0cf09246e",
+    },
+}
+
+
+def measured_traffic(config: str, kernel: str):
+    import hashlib
+
+    t = TRAFFIC.get((config, kernel))
+    if t is None:
+        return None
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, "paper_2302_03317_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t["sha256"]:
+        return None
+    return t["read_bytes"] + t["write_bytes"]
+
 
 def fill_identity(t, n, w, torch):
     """Identity contents written on the GPU in chunks (element i holds i)."""
@@ -253,6 +282,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="u32_2e32", choices=sorted(CONFIGS) + ["serve_u64"])
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="before the timed region, copy the array once device-to-device (a plain "
+                         "copy of known size for scaling HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rates", default="1000,2000,4000,8000,16000")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
@@ -296,6 +328,12 @@ def main() -> int:
         t = torch.empty((n, 2), dtype=torch.int64, device=dev)
     fill_identity(t, n, w, torch)
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        u = torch.empty_like(t)
+        u.copy_(t)
+        torch.cuda.synchronize()
+        del u
+        torch.cuda.empty_cache()
     before = checksum(t, torch)
     params = shuf.default_params(n, w)
 
@@ -341,7 +379,7 @@ def main() -> int:
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        "traffic": None,
+        "traffic": measured_traffic(args.config, dom),
         "bytes_per_launch": per_launch_bytes,
         "avg_launch_ms": per_launch_s * 1e3,
     }
