@@ -284,3 +284,70 @@ def test_session_result_same_alone_and_in_mix():
         shuf.shuffle_inplace_ex(alone, seed, sid)
         torch.cuda.synchronize()
         assert_same(from_dev(alone, h), want, f"alone {tk}")
+
+
+def test_full_size_u32_2e28_equals_oracle():
+    """The width-sweep size, default parameters, element by element against
+    the oracle (about 20 s of single-core CPU work)."""
+    n, w = 1 << 28, 4
+    seed = 0xC0FFEE1234567
+    host = workloads.identity(n, w)
+    print(f"[gpu] full size n=2^28 u32 seed={seed}", flush=True)
+    got = gpu_shuffle(host, seed, None)
+    want = oracle_shuffle(host, seed, oracle.default_params(n, w))
+    assert_same(got, want, "2^28 u32")
+
+
+def _is_identity_permutation(t, n):
+    """Every value 0..n-1 occurs exactly once in t (checked in chunks)."""
+    seen = torch.zeros(n, dtype=torch.uint8, device=t.device)
+    flat = t.view(-1) if t.dim() == 1 else t[:, 0]
+    chunk = 1 << 27
+    for a in range(0, n, chunk):
+        idx = flat[a:a + chunk].to(torch.int64)
+        if t.dtype == torch.int32:
+            idx = idx & 0xFFFFFFFF
+        if bool(((idx < 0) | (idx >= n)).any()):
+            return False
+        seen.index_fill_(0, idx, 1)
+        del idx
+    return bool(seen.all())
+
+
+@pytest.mark.parametrize("log2n,w", [(32, 4), (31, 8)])
+def test_full_size_properties(log2n, w):
+    """The single-array headline sizes in the benchmark's launch
+    configuration: the output is a permutation of the input, a rerun with
+    the same seed gives the same bytes, another stream id does not, and the
+    number of fixed points is small (Poisson(1) for a uniform permutation)."""
+    shuf = _lib()
+    dev = _dev()
+    n = 1 << log2n
+    dt = torch.int32 if w == 4 else torch.int64
+    print(f"[gpu] full size properties n=2^{log2n} w={w}", flush=True)
+    a = torch.empty(n, dtype=dt, device=dev)
+    chunk = 1 << 27
+    for s in range(0, n, chunk):
+        a[s:s + chunk] = torch.arange(s, min(n, s + chunk), device=dev, dtype=torch.int64).to(dt)
+    b = a.clone()
+    seed = 0x5151AB
+    shuf.shuffle_inplace(a, seed)
+    shuf.shuffle_inplace(b, seed)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    fixed = 0
+    for s in range(0, n, chunk):
+        ar = torch.arange(s, min(n, s + chunk), device=dev, dtype=torch.int64)
+        v = a[s:s + chunk].to(torch.int64)
+        if dt == torch.int32:
+            v = v & 0xFFFFFFFF
+        fixed += int((v == ar).sum())
+    assert fixed < 20, fixed
+    assert _is_identity_permutation(a, n)
+    del b
+    c = torch.empty_like(a)
+    for s in range(0, n, chunk):
+        c[s:s + chunk] = torch.arange(s, min(n, s + chunk), device=dev, dtype=torch.int64).to(dt)
+    shuf.shuffle_inplace_ex(c, seed, 1)
+    torch.cuda.synchronize()
+    assert not torch.equal(a, c)
