@@ -90,6 +90,30 @@ int shuffle_inplace(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, v
 int shuffle_inplace_ex(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed,
                        uint32_t stream_id, const shuf_params_t* params, void* stream);
 
+/* Exact device workspace, in bytes, that shuffle_inplace_ws needs for these
+ * arguments (the permutation's recursion depends on the seed and stream id,
+ * not on the data).  It runs the planning part of the shuffle on the device
+ * (labels counted per tile, the level tables) without touching any element,
+ * using the library's own memory; it takes some of the time of a shuffle.
+ * *out_bytes = 0 for n <= 1.  Errors: SHUF_EINVAL (NULL out_bytes, bad width
+ * or parameters), SHUF_EUNSUPPORTED, SHUF_ENOMEM, SHUF_EHIP. */
+int shuffle_workspace_bytes(uint64_t n, uint32_t elem_bytes, uint64_t seed, uint32_t stream_id,
+                            const shuf_params_t* params, uint64_t* out_bytes, void* stream);
+
+/* As shuffle_inplace_ex, with every per-level device buffer (the movers of a
+ * level and all level tables) carved from the caller's `workspace` of
+ * `workspace_bytes` bytes, 256-byte aligned, owned by the caller and not
+ * touched after the call returns.  The library still keeps its leaf lists
+ * (48 bytes per finished subproblem) and pinned staging in its own pools.
+ * `workspace_bytes` must be at least what shuffle_workspace_bytes reports for
+ * the same (n, elem_bytes, seed, stream_id, params); a smaller workspace fails
+ * with SHUF_ENOMEM, possibly after the data has been partly permuted.
+ * Additional errors: SHUF_EINVAL for a misaligned workspace, or NULL with
+ * workspace_bytes > 0. */
+int shuffle_inplace_ws(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                       uint32_t stream_id, const shuf_params_t* params, void* workspace,
+                       uint64_t workspace_bytes, void* stream);
+
 /* Shuffle `count` independent arrays packed back to back at ptr, each in
  * place.  Array j occupies elements [offsets[j], offsets[j+1]) and is shuffled
  * exactly as shuffle_inplace_ex(ptr + offsets[j] * elem_bytes,

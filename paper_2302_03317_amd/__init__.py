@@ -104,6 +104,11 @@ def lib() -> ctypes.CDLL:
         L.shuffle_inplace_ex.restype = i
         L.shuffle_batched.argtypes = [vp, ctypes.POINTER(u64), u64, u32, u64, vp]
         L.shuffle_batched.restype = i
+        L.shuffle_workspace_bytes.argtypes = [u64, u32, u64, u32, ctypes.POINTER(_Params),
+                                              ctypes.POINTER(u64), vp]
+        L.shuffle_workspace_bytes.restype = i
+        L.shuffle_inplace_ws.argtypes = [vp, u64, u32, u64, u32, ctypes.POINTER(_Params), vp, u64, vp]
+        L.shuffle_inplace_ws.restype = i
         L.shuffle_many.argtypes = [ctypes.POINTER(_Array), u64, u32, vp]
         L.shuffle_many.restype = i
         L.shuf_session_create.argtypes = [u32, ctypes.POINTER(vp)]
@@ -187,6 +192,40 @@ def shuffle_inplace_ex(tensor, seed: int, stream_id: int = 0, params: Params | N
     )
     if rc != SHUF_OK:
         raise ShuffleError(rc, "shuffle_inplace_ex")
+
+
+def workspace_bytes(n: int, elem_bytes: int, seed: int, stream_id: int = 0,
+                    params: Params | None = None, stream=None) -> int:
+    """Exact device workspace shuffle_inplace_ws needs for these arguments."""
+    p = params if params is not None else default_params(n, elem_bytes)
+    cp = _Params(p.tile, p.kmax_log2, p.n0, p.lmax)
+    out = ctypes.c_uint64()
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream()
+    sh = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    rc = lib().shuffle_workspace_bytes(n, elem_bytes, seed & (2**64 - 1), stream_id, ctypes.byref(cp),
+                                       ctypes.byref(out), sh)
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_workspace_bytes")
+    return int(out.value)
+
+
+def shuffle_inplace_ws(tensor, seed: int, workspace, stream_id: int = 0,
+                       params: Params | None = None, stream=None) -> None:
+    """Shuffle with every per-level device buffer taken from `workspace` (a
+    GPU tensor of at least workspace_bytes(...) bytes)."""
+    n, w = _geometry(tensor)
+    p = params if params is not None else default_params(n, w)
+    cp = _Params(p.tile, p.kmax_log2, p.n0, p.lmax)
+    wb = workspace.numel() * workspace.element_size()
+    rc = lib().shuffle_inplace_ws(
+        ctypes.c_void_p(tensor.data_ptr()), n, w, seed & (2**64 - 1), stream_id, ctypes.byref(cp),
+        ctypes.c_void_p(workspace.data_ptr()), wb, _stream_handle(tensor, stream),
+    )
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_inplace_ws")
 
 
 def shuffle_batched(tensor, offsets, seed: int, stream=None) -> None:

@@ -83,6 +83,34 @@ hipError_t grow_keep(DevBuf& d, size_t bytes, size_t used, hipStream_t s)
     return hipSuccess;
 }
 
+// Where a step's device buffers come from: the device's pools (grown as
+// needed and kept), a caller's workspace (a region reused by every step), or
+// the pools while recording the largest step (planning a workspace).
+struct Mem {
+    enum Mode { kPool, kArena, kTally } mode = kPool;
+    uint8_t* base = nullptr;
+    uint64_t size = 0, off = 0, peak = 0;
+    static uint64_t align(uint64_t b) { return (b + 255) & ~static_cast<uint64_t>(255); }
+    void begin_step() { off = 0; }
+    hipError_t take(DevBuf& pool, uint64_t bytes, void** out)
+    {
+        if (mode == kArena) {
+            if (off + align(bytes) > size) return hipErrorOutOfMemory;
+            *out = base + off;
+            off += align(bytes);
+            return hipSuccess;
+        }
+        const hipError_t e = pool.ensure(bytes);
+        if (e != hipSuccess) return e;
+        *out = pool.p;
+        if (mode == kTally) {
+            off += align(bytes);
+            peak = std::max(peak, off);
+        }
+        return hipSuccess;
+    }
+};
+
 struct HostBuf {
     void* p = nullptr;
     size_t cap = 0;
@@ -242,17 +270,20 @@ int hip_error_code(hipError_t e)
     return e == hipErrorOutOfMemory ? SHUF_ENOMEM : SHUF_EHIP;
 }
 
+// Copy a host vector to a device buffer taken from `mem` (staged through a
+// pinned buffer); *out receives the device pointer.
 template <typename T>
-hipError_t upload(DevBuf& d, HostBuf& h, const std::vector<T>& v, hipStream_t s)
+hipError_t upload(Mem& mem, DevBuf& d, HostBuf& h, const std::vector<T>& v, hipStream_t s,
+                  void** out)
 {
     const size_t bytes = v.size() * sizeof(T);
-    hipError_t e = d.ensure(bytes);
+    hipError_t e = mem.take(d, bytes, out);
     if (e != hipSuccess) return e;
     e = h.ensure(bytes);
     if (e != hipSuccess) return e;
     if (bytes == 0) return hipSuccess;
     std::memcpy(h.p, v.data(), bytes);
-    return hipMemcpyAsync(d.p, h.p, bytes, hipMemcpyHostToDevice, s);
+    return hipMemcpyAsync(*out, h.p, bytes, hipMemcpyHostToDevice, s);
 }
 
 // Work of one engine: subproblems waiting for a tiled level and leaves
@@ -275,6 +306,19 @@ struct Engine {
     std::vector<uint64_t> done_queue;
     uint64_t next_ticket = 1, inflight = 0;
     bool broken = false;
+    bool dry = false;  // planning run: counts and tables only, no element moves
+    Mem mem;
+};
+
+// Timing off for the duration of a planning step.
+struct TimingOff {
+    Context& C;
+    bool was;
+    TimingOff(Context& c, bool off) : C(c), was(c.timing)
+    {
+        if (off) C.timing = false;
+    }
+    ~TimingOff() { C.timing = was; }
 };
 
 uint64_t engine_submit(Engine& E, uint64_t elem_addr, uint64_t n, uint64_t seed, uint32_t stream_id)
@@ -312,14 +356,19 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     }
     const uint32_t kmax = 1u << prm.kmax_log2;
     const uint64_t tile_limit = prm.tile - kmax;  // subproblems up to this size finish in LDS
-    HIP_TRY(C.err.ensure(4));
+    const bool dry = E.dry;
+    TimingOff timing_guard(C, dry);
+    Mem& mem = E.mem;
+    mem.begin_step();
+    void *p_err, *p_counters, *p_total;
+    HIP_TRY(mem.take(C.err, 4, &p_err));
     HIP_TRY(C.h_err.ensure(4));
-    HIP_TRY(hipMemsetAsync(C.err.p, 0, 4, stream));
-    HIP_TRY(C.counters.ensure(48));
+    HIP_TRY(hipMemsetAsync(p_err, 0, 4, stream));
+    HIP_TRY(mem.take(C.counters, 48, &p_counters));
     HIP_TRY(C.h_counters.ensure(48));
-    HIP_TRY(C.total.ensure(8));
+    HIP_TRY(mem.take(C.total, 8, &p_total));
     HIP_TRY(C.h_total.ensure(8));
-    unsigned long long* dc = static_cast<unsigned long long*>(C.counters.p);
+    unsigned long long* dc = static_cast<unsigned long long*>(p_counters);
     unsigned long long* hc = C.h_counters.as<unsigned long long>();
     // [0] leaf children, [1] big children, [2] leaf child elements, [3..5] leaves per class
     HIP_TRY(hipMemsetAsync(dc, 0, 48, stream));
@@ -343,10 +392,12 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     const LeafDesc* leaves_now = static_cast<const LeafDesc*>(E.lists->leaves[E.which].p);
     uint32_t caps[3];
     leaf_class_caps(w, prm, caps);
+    void* p_cls = nullptr;
     if (run_leaves) {
-        HIP_TRY(C.leaves_cls.ensure(3 * run_leaves * sizeof(LeafDesc)));
-        HIP_TRY(launch_leaf_classes(leaves_now, run_leaves, static_cast<LeafDesc*>(C.leaves_cls.p),
-                                    run_leaves, caps, dc + 3, stream));
+        HIP_TRY(mem.take(C.leaves_cls, 3 * run_leaves * sizeof(LeafDesc), &p_cls));
+        if (!dry)
+            HIP_TRY(launch_leaf_classes(leaves_now, run_leaves, static_cast<LeafDesc*>(p_cls),
+                                        run_leaves, caps, dc + 3, stream));
     }
 
     // Tiled level of every waiting subproblem; the recursion cap sends a
@@ -367,6 +418,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     std::vector<SubDesc> subs;
     std::vector<uint32_t> tile_sub, chunk_sub, bk_sub;
     LevelTables T{};
+    void* p_big = nullptr;
     uint64_t ntiles = 0;
     if (!tiled.empty()) {
         uint64_t tab = 0, nchunks = 0, chtab = 0, nbk = 0;
@@ -410,46 +462,50 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
             std::fill(bk_sub.begin() + d.bk_off, bk_sub.begin() + d.bk_off + (1u << d.kappa), i);
             level_elems += d.m;
         }
-        HIP_TRY(upload(C.subs, C.h_subs, subs, stream));
-        HIP_TRY(upload(C.tile_sub, C.h_tile_sub, tile_sub, stream));
-        HIP_TRY(upload(C.chunk_sub, C.h_chunk_sub, chunk_sub, stream));
-        HIP_TRY(upload(C.bk_sub, C.h_bk_sub, bk_sub, stream));
-        HIP_TRY(C.cnt.ensure(tab * 4));
-        HIP_TRY(C.mpre.ensure(tab * 8));
-        HIP_TRY(C.kpre.ensure(tab * 8));
-        HIP_TRY(C.chA.ensure(chtab * 8));
-        HIP_TRY(C.chB.ensure(chtab * 8));
-        HIP_TRY(C.N.ensure(nbk * 8));
-        HIP_TRY(C.S.ensure(nbk * 8));
-        HIP_TRY(C.M.ensure(nbk * 8));
-        HIP_TRY(C.K.ensure(nbk * 8));
-        HIP_TRY(C.MB.ensure(nbk * 8));
-        HIP_TRY(C.wsp.ensure((nbk / kScanChunk + 2) * 8));
+        void *p_subs, *p_tile_sub, *p_chunk_sub, *p_bk_sub, *p_cnt, *p_mpre, *p_kpre, *p_chA, *p_chB,
+            *p_N, *p_S, *p_M, *p_K, *p_MB, *p_wsp;
+        HIP_TRY(upload(mem, C.subs, C.h_subs, subs, stream, &p_subs));
+        HIP_TRY(upload(mem, C.tile_sub, C.h_tile_sub, tile_sub, stream, &p_tile_sub));
+        HIP_TRY(upload(mem, C.chunk_sub, C.h_chunk_sub, chunk_sub, stream, &p_chunk_sub));
+        HIP_TRY(upload(mem, C.bk_sub, C.h_bk_sub, bk_sub, stream, &p_bk_sub));
+        HIP_TRY(mem.take(C.cnt, tab * 4, &p_cnt));
+        HIP_TRY(mem.take(C.mpre, tab * 8, &p_mpre));
+        HIP_TRY(mem.take(C.kpre, tab * 8, &p_kpre));
+        HIP_TRY(mem.take(C.chA, chtab * 8, &p_chA));
+        HIP_TRY(mem.take(C.chB, chtab * 8, &p_chB));
+        HIP_TRY(mem.take(C.N, nbk * 8, &p_N));
+        HIP_TRY(mem.take(C.S, nbk * 8, &p_S));
+        HIP_TRY(mem.take(C.M, nbk * 8, &p_M));
+        HIP_TRY(mem.take(C.K, nbk * 8, &p_K));
+        HIP_TRY(mem.take(C.MB, nbk * 8, &p_MB));
+        HIP_TRY(mem.take(C.wsp, (nbk / kScanChunk + 2) * 8, &p_wsp));
         HIP_TRY(E.lists->leaves[1 - E.which].ensure(nbk * sizeof(LeafDesc)));
-        HIP_TRY(C.big.ensure(nbk * sizeof(LeafDesc)));
+        HIP_TRY(mem.take(C.big, nbk * sizeof(LeafDesc), &p_big));
 
-        T.subs = static_cast<const SubDesc*>(C.subs.p);
-        T.tile_sub = static_cast<const uint32_t*>(C.tile_sub.p);
-        T.chunk_sub = static_cast<const uint32_t*>(C.chunk_sub.p);
-        T.bk_sub = static_cast<const uint32_t*>(C.bk_sub.p);
-        T.cnt = static_cast<uint32_t*>(C.cnt.p);
-        T.mpre = static_cast<uint64_t*>(C.mpre.p);
-        T.kpre = static_cast<uint64_t*>(C.kpre.p);
-        T.chA = static_cast<uint64_t*>(C.chA.p);
-        T.chB = static_cast<uint64_t*>(C.chB.p);
-        T.N = static_cast<uint64_t*>(C.N.p);
-        T.S = static_cast<uint64_t*>(C.S.p);
-        T.M = static_cast<uint64_t*>(C.M.p);
-        T.K = static_cast<uint64_t*>(C.K.p);
-        T.MB = static_cast<uint64_t*>(C.MB.p);
-        T.wsp = static_cast<uint64_t*>(C.wsp.p);
-        T.total = static_cast<uint64_t*>(C.total.p);
-        T.err = static_cast<uint32_t*>(C.err.p);
+        T.subs = static_cast<const SubDesc*>(p_subs);
+        T.tile_sub = static_cast<const uint32_t*>(p_tile_sub);
+        T.chunk_sub = static_cast<const uint32_t*>(p_chunk_sub);
+        T.bk_sub = static_cast<const uint32_t*>(p_bk_sub);
+        T.cnt = static_cast<uint32_t*>(p_cnt);
+        T.mpre = static_cast<uint64_t*>(p_mpre);
+        T.kpre = static_cast<uint64_t*>(p_kpre);
+        T.chA = static_cast<uint64_t*>(p_chA);
+        T.chB = static_cast<uint64_t*>(p_chB);
+        T.N = static_cast<uint64_t*>(p_N);
+        T.S = static_cast<uint64_t*>(p_S);
+        T.M = static_cast<uint64_t*>(p_M);
+        T.K = static_cast<uint64_t*>(p_K);
+        T.MB = static_cast<uint64_t*>(p_MB);
+        T.wsp = static_cast<uint64_t*>(p_wsp);
+        T.total = static_cast<uint64_t*>(p_total);
+        T.err = static_cast<uint32_t*>(p_err);
         T.nsubs = nsub;
         T.ntiles = ntiles;
         T.nchunks = nchunks;
         T.nbuckets = nbk;
-        {
+        if (dry) {
+            HIP_TRY(launch_count(T.subs, T.tile_sub, T.cnt, ntiles, stream));
+        } else {
             SpanGuard g(C, stream, 0, 2.0 * level_elems * w);
             HIP_TRY(launch_rough(w, T.subs, T.tile_sub, T.cnt, ntiles, prm, stream));
         }
@@ -459,7 +515,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
             HIP_TRY(launch_tables_routes(T, stream));
             HIP_TRY(launch_children(T, static_cast<uint32_t>(tile_limit),
                                     static_cast<LeafDesc*>(E.lists->leaves[1 - E.which].p),
-                                    static_cast<LeafDesc*>(C.big.p), dc, stream));
+                                    static_cast<LeafDesc*>(p_big), dc, stream));
         }
         HIP_TRY(hipMemcpyAsync(C.h_total.p, T.total, 8, hipMemcpyDeviceToHost, stream));
     }
@@ -467,7 +523,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     HIP_TRY(hipStreamSynchronize(stream));
     const uint64_t child_leaves = hc[0], nbig = hc[1], child_elems = hc[2];
     const uint64_t count[3] = {hc[3], hc[4], hc[5]};
-    if (run_leaves && count[0] + count[1] + count[2] != run_leaves) {
+    if (!dry && run_leaves && count[0] + count[1] + count[2] != run_leaves) {
         E.broken = true;
         return SHUF_EHIP;
     }
@@ -476,7 +532,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
         const uint64_t movers = C.h_total.as<uint64_t>()[0];
         if (nbig) {
             HIP_TRY(C.h_big.ensure(nbig * sizeof(LeafDesc)));
-            HIP_TRY(hipMemcpyAsync(C.h_big.p, C.big.p, nbig * sizeof(LeafDesc),
+            HIP_TRY(hipMemcpyAsync(C.h_big.p, p_big, nbig * sizeof(LeafDesc),
                                    hipMemcpyDeviceToHost, stream));
             HIP_TRY(hipStreamSynchronize(stream));
             const LeafDesc* bl = C.h_big.as<LeafDesc>();
@@ -488,34 +544,40 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
                 return a.elem_off != b.elem_off ? a.elem_off < b.elem_off : a.base < b.base;
             });
         }
-        HIP_TRY(C.ws.ensure(std::max<uint64_t>(movers, 1) * w));
+        void* p_ws;
+        HIP_TRY(mem.take(C.ws, std::max<uint64_t>(movers, 1) * w, &p_ws));
         T.ws_cap = movers;
-        {
-            SpanGuard g(C, stream, 2, 2.0 * movers * w);
-            HIP_TRY(launch_gather(w, static_cast<uint8_t*>(C.ws.p), T, stream));
-        }
-        {
-            SpanGuard g(C, stream, 3, 2.0 * movers * w);
-            HIP_TRY(launch_scatter(w, static_cast<const uint8_t*>(C.ws.p), T, stream));
+        if (!dry) {
+            {
+                SpanGuard g(C, stream, 2, 2.0 * movers * w);
+                HIP_TRY(launch_gather(w, static_cast<uint8_t*>(p_ws), T, stream));
+            }
+            {
+                SpanGuard g(C, stream, 3, 2.0 * movers * w);
+                HIP_TRY(launch_scatter(w, static_cast<const uint8_t*>(p_ws), T, stream));
+            }
         }
         st.tiled_levels++;
         st.tiles += ntiles;
         st.movers += movers;
         st.workspace_bytes = std::max<uint64_t>(st.workspace_bytes, movers * w);
     }
-    if (run_leaves) {
+    if (run_leaves && !dry) {
         SpanGuard g(C, stream, 4, 2.0 * static_cast<double>(run_leaf_elems) * w);
-        HIP_TRY(launch_leaf(w, static_cast<const LeafDesc*>(C.leaves_cls.p), count, run_leaves, prm,
-                            caps, stream));
+        HIP_TRY(launch_leaf(w, static_cast<const LeafDesc*>(p_cls), count, run_leaves, prm, caps,
+                            stream));
     }
     if (!gfy.empty()) {
-        HIP_TRY(upload(C.gfy, C.h_gfy, gfy, stream));
+        void* p_gfy;
+        HIP_TRY(upload(mem, C.gfy, C.h_gfy, gfy, stream, &p_gfy));
         uint64_t elems = 0;
         for (const LeafDesc& l : gfy) elems += l.m;
-        SpanGuard g(C, stream, 5, 2.0 * elems * w);
-        HIP_TRY(launch_fy_global(w, static_cast<const LeafDesc*>(C.gfy.p), gfy.size(), stream));
+        if (!dry) {
+            SpanGuard g(C, stream, 5, 2.0 * elems * w);
+            HIP_TRY(launch_fy_global(w, static_cast<const LeafDesc*>(p_gfy), gfy.size(), stream));
+        }
     }
-    HIP_TRY(hipMemcpyAsync(C.h_err.p, C.err.p, 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(C.h_err.p, p_err, 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     if (C.h_err.as<uint32_t>()[0] != 0) {  // an index check failed in a kernel
         E.broken = true;
@@ -562,7 +624,7 @@ int engine_drain(Engine& E, void* stream)
         const int rc = engine_step(*C, E, static_cast<hipStream_t>(stream), st);
         if (rc != SHUF_OK) return rc;
     }
-    C->stats = st;
+    if (!E.dry) C->stats = st;
     return SHUF_OK;
 }
 
@@ -605,6 +667,46 @@ int shuffle_inplace_ex(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed
     if (reinterpret_cast<uintptr_t>(ptr) % elem_bytes) return SHUF_EINVAL;
     if (n >= kMaxElements) return SHUF_EUNSUPPORTED;
     Engine E = make_engine(elem_bytes, *params);
+    engine_submit(E, reinterpret_cast<uintptr_t>(ptr) / elem_bytes, n, seed, stream_id);
+    return engine_drain(E, stream);
+}
+
+int shuffle_workspace_bytes(uint64_t n, uint32_t elem_bytes, uint64_t seed, uint32_t stream_id,
+                            const shuf_params_t* params, uint64_t* out_bytes, void* stream)
+{
+    if (!out_bytes || !valid_width(elem_bytes)) return SHUF_EINVAL;
+    int rc = check_params(params, elem_bytes);
+    if (rc != SHUF_OK) return rc;
+    *out_bytes = 0;
+    if (n <= 1) return SHUF_OK;
+    if (n >= kMaxElements) return SHUF_EUNSUPPORTED;
+    Engine E = make_engine(elem_bytes, *params);
+    E.dry = true;
+    E.mem.mode = Mem::kTally;
+    engine_submit(E, 0, n, seed, stream_id);  // a planning run never touches elements
+    rc = engine_drain(E, stream);
+    if (rc != SHUF_OK) return rc;
+    *out_bytes = E.mem.peak;
+    return SHUF_OK;
+}
+
+int shuffle_inplace_ws(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                       uint32_t stream_id, const shuf_params_t* params, void* workspace,
+                       uint64_t workspace_bytes, void* stream)
+{
+    if (!valid_width(elem_bytes)) return SHUF_EINVAL;
+    int rc = check_params(params, elem_bytes);
+    if (rc != SHUF_OK) return rc;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return SHUF_EINVAL;
+    if (!workspace && workspace_bytes) return SHUF_EINVAL;
+    if (n <= 1) return SHUF_OK;
+    if (!ptr) return SHUF_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ptr) % elem_bytes) return SHUF_EINVAL;
+    if (n >= kMaxElements) return SHUF_EUNSUPPORTED;
+    Engine E = make_engine(elem_bytes, *params);
+    E.mem.mode = Mem::kArena;
+    E.mem.base = static_cast<uint8_t*>(workspace);
+    E.mem.size = workspace_bytes;
     engine_submit(E, reinterpret_cast<uintptr_t>(ptr) / elem_bytes, n, seed, stream_id);
     return engine_drain(E, stream);
 }

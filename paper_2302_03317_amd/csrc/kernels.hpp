@@ -19,6 +19,9 @@ struct __attribute__((aligned(16))) Elem16 {
 hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_sub,
                         uint32_t* cnt_tab, uint64_t ntiles, const Params& prm, hipStream_t stream);
 hipError_t set_rough_lds_limits();
+// The count table of one tiled level without moving elements (planning).
+hipError_t launch_count(const SubDesc* subs, const uint32_t* tile_sub, uint32_t* cnt_tab,
+                        uint64_t ntiles, hipStream_t stream);
 
 // Device tables of one tiled level (see k_fixup.hip).
 struct LevelTables {

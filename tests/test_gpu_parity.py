@@ -351,3 +351,38 @@ def test_full_size_properties(log2n, w):
     shuf.shuffle_inplace_ex(c, seed, 1)
     torch.cuda.synchronize()
     assert not torch.equal(a, c)
+
+
+@pytest.mark.parametrize(
+    "n,w,p",
+    [
+        (3_000_017, 4, None),
+        (1_000_000, 8, None),
+        (400_000, 16, None),
+        (500_000, 4, oracle.Params(300, 2, 5, 32)),
+        (10_000, 4, None),
+    ],
+)
+def test_caller_workspace_is_exact_and_sufficient(n, w, p):
+    """shuffle_workspace_bytes is exact: the caller-workspace shuffle succeeds
+    with that many bytes (and equals the oracle), and fails with SHUF_ENOMEM
+    with one byte less."""
+    shuf = _lib()
+    host = workloads.identity(n, w)
+    params = p if p is not None else oracle.default_params(n, w)
+    sp = shuf.Params(params.tile, params.kmax_log2, params.n0, params.lmax)
+    seed, sid = 0xABCDEF ^ n, 3
+    need = shuf.workspace_bytes(n, w, seed, sid, sp)
+    print(f"[gpu] workspace n={n} w={w} params={params} bytes={need}", flush=True)
+    assert need > 0
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=_dev())
+    t = to_dev(host)
+    shuf.shuffle_inplace_ws(t, seed, ws, sid, sp)
+    torch.cuda.synchronize()
+    assert_same(from_dev(t, host), oracle_shuffle(host, seed, params, stream_id=sid), f"ws n={n} w={w}")
+    small = ws[: need - 1]
+    t2 = to_dev(host)
+    with pytest.raises(shuf.ShuffleError) as ei:
+        shuf.shuffle_inplace_ws(t2, seed, small, sid, sp)
+    assert ei.value.code == shuf.SHUF_ENOMEM
+    torch.cuda.synchronize()

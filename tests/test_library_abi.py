@@ -90,3 +90,22 @@ def test_multi_array_and_session_argument_checks_without_gpu():
     assert lib.shuf_session_inflight(None, ctypes.byref(nd), None) == shuf.SHUF_EINVAL
     assert lib.shuf_session_create(3, None) == shuf.SHUF_EINVAL
     assert lib.shuf_session_destroy(None) == shuf.SHUF_EINVAL
+
+
+def test_workspace_calls_argument_checks_without_gpu():
+    shuf = _lib()
+    lib = shuf.lib()
+    null = ctypes.c_void_p(0)
+    p = shuf._Params(16384, 8, 64, 32)
+    out = ctypes.c_uint64(123)
+    assert lib.shuffle_workspace_bytes(1000, 4, 1, 0, ctypes.byref(p), None, null) == shuf.SHUF_EINVAL
+    assert lib.shuffle_workspace_bytes(1000, 3, 1, 0, ctypes.byref(p), ctypes.byref(out), null) == shuf.SHUF_EINVAL
+    assert lib.shuffle_workspace_bytes(1000, 4, 1, 0, None, ctypes.byref(out), null) == shuf.SHUF_EINVAL
+    assert lib.shuffle_workspace_bytes(1, 4, 1, 0, ctypes.byref(p), ctypes.byref(out), null) == 0
+    assert out.value == 0
+    ptr = ctypes.c_void_p(0x10000)
+    ws = ctypes.c_void_p(0x20000)
+    assert lib.shuffle_inplace_ws(ptr, 1000, 4, 1, 0, ctypes.byref(p), ctypes.c_void_p(0x20010), 4096, null) == shuf.SHUF_EINVAL
+    assert lib.shuffle_inplace_ws(ptr, 1000, 4, 1, 0, ctypes.byref(p), null, 4096, null) == shuf.SHUF_EINVAL
+    assert lib.shuffle_inplace_ws(ctypes.c_void_p(0x10002), 1000, 4, 1, 0, ctypes.byref(p), ws, 4096, null) == shuf.SHUF_EINVAL
+    assert lib.shuffle_inplace_ws(null, 1, 4, 1, 0, ctypes.byref(p), null, 0, null) == 0
