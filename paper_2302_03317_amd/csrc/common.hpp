@@ -68,6 +68,13 @@ struct LeafDesc {
 // that it stays inside 64 bits (the host ensures P <= 2^32).
 __host__ __device__ __forceinline__ uint64_t piece_offset(uint64_t t, uint64_t len, uint64_t P)
 {
+    if (((len | P) >> 32) == 0) {  // 32-bit divisions where the operands allow
+        const uint32_t l32 = static_cast<uint32_t>(len), p32 = static_cast<uint32_t>(P);
+        const uint32_t q = l32 / p32, r = l32 % p32;
+        const uint64_t tr = t * r;
+        const uint64_t rest = (tr >> 32) == 0 ? static_cast<uint32_t>(tr) / p32 : tr / P;
+        return t * q + rest;
+    }
     const uint64_t q = len / P, r = len % P;
     return t * q + (t * r) / P;
 }

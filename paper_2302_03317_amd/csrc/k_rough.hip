@@ -30,19 +30,31 @@ template <int KAPPA, int R>
 __device__ __forceinline__ void rank_rounds(const uint8_t* lab, uint32_t* Hw, uint32_t first,
                                             uint32_t ts, uint32_t (&pk)[R])
 {
+    // labels of eight rounds are read ahead (slots past the tile read slot 0)
+    constexpr int kAhead = R < 8 ? R : 8;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t q = first + 64u * r;
-        uint32_t v = 0;
-        if (q < ts) {
-            const uint32_t l = lab[q];
-            const uint64_t peers = match_label_bits<KAPPA>(l);
-            const uint32_t below = bits_below(peers);
-            const uint32_t old = Hw[l];
-            if (below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
-            v = l | ((old + below) << 8);
+    for (int r0 = 0; r0 < R; r0 += kAhead) {
+        uint32_t lb[kAhead];
+#pragma unroll
+        for (int i = 0; i < kAhead; ++i) {
+            const uint32_t q = first + 64u * (r0 + i);
+            lb[i] = lab[q < ts ? q : 0u];
         }
-        pk[r] = v;
+#pragma unroll
+        for (int i = 0; i < kAhead; ++i) {
+            const int r = r0 + i;
+            const uint32_t q = first + 64u * r;
+            uint32_t v = 0;
+            if (q < ts) {
+                const uint32_t l = lb[i];
+                const uint64_t peers = match_label_bits<KAPPA>(l);
+                const uint32_t below = bits_below(peers);
+                const uint32_t old = Hw[l];
+                if (below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
+                v = l | ((old + below) << 8);
+            }
+            pk[r] = v;
+        }
     }
 }
 
@@ -125,11 +137,13 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
     // Wave wv owns read-order slots [wv * 64R, (wv + 1) * 64R); round r gives
     // lane l the slot wv * 64R + 64r + l.
     const uint32_t first = wv * 64u * R + lane;
+    // Reads of slots past the tile's end fetch slot 0 (in bounds, unused) so
+    // that the loop has no branches and its reads overlap.
     E data[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t q = first + 64u * r;
-        if (q < ts) data[r] = stage[q];
+        data[r] = stage[q < ts ? q : 0u];
     }
     __syncthreads();  // staging is free: labels and per-wave counters overlay it
 
@@ -201,9 +215,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
     const uint32_t nfree = hot[k];
     const bool use_list = nfree <= prm.tile / 2;
     if (use_list) {
-        for (uint32_t b = wv; b < k; b += kWaves) {
+        for (uint32_t b = tid; b < k; b += kThreads) {
             const uint32_t base = hot[b], f0 = qoff[b] + fill[b], nh = cap[b] - fill[b];
-            for (uint32_t j = lane; j < nh; j += 64) fs[base + j] = static_cast<uint16_t>(f0 + j);
+            for (uint32_t j = 0; j < nh; ++j) fs[base + j] = static_cast<uint16_t>(f0 + j);
         }
     }
     for (uint32_t i = tid; i < kWaves * k; i += kThreads) {
@@ -218,16 +232,18 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
 
     // Destination slot in staging order.
     if (use_list) {
+        // every round, also those past the tile (pk = 0 there: label 0,
+        // rank 0), so that the reads of all rounds overlap; every read stays
+        // inside the table and the free list
+        const uint32_t fmax = nfree ? nfree - 1 : 0u;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const uint32_t q = first + 64u * r;
-            if (q < ts) {
-                const uint32_t l = pk[r] & 0xFFu, rr = pk[r] >> 8;
-                const uint2 e = WT[wv * k + l];
-                const bool placed = static_cast<int32_t>(rr) < (static_cast<int32_t>(e.x) >> 16);
-                const uint32_t f = fs[placed ? 0u : e.y + rr];
-                pk[r] = placed ? (e.x & 0xFFFFu) + rr : f;
-            }
+            const uint32_t l = pk[r] & 0xFFu, rr = pk[r] >> 8;
+            const uint2 e = WT[wv * k + (l & (k - 1))];
+            const bool placed = static_cast<int32_t>(rr) < (static_cast<int32_t>(e.x) >> 16);
+            const uint32_t fi = e.y + rr;
+            const uint32_t f = fs[placed ? 0u : (fi < fmax ? fi : fmax)];
+            pk[r] = placed ? (e.x & 0xFFFFu) + rr : f;
         }
     } else {
 #pragma unroll
