@@ -100,14 +100,15 @@ __device__ __forceinline__ uint32_t half_of(const Word4& v, uint32_t h)
 __device__ __forceinline__ uint32_t fy_short_draw(const Key& key, uint32_t level, uint64_t pos,
                                                   uint32_t bound, uint32_t first_word)
 {
-    uint32_t prod = first_word * bound;
+    // 16-bit word times a bound <= 2^16: both fit 24 bits, the product 32
+    uint32_t prod = __umul24(first_word, bound);
     if ((prod & 0xFFFFu) < bound) {
         const uint32_t threshold = 0x10000u % bound;
         uint32_t attempt = 0;
         while ((prod & 0xFFFFu) < threshold && attempt < 65535u) {
             ++attempt;
             const Word4 v = fy_short_block(key, level, pos >> 3, attempt);
-            prod = half_of(v, static_cast<uint32_t>(pos & 7)) * bound;
+            prod = __umul24(half_of(v, static_cast<uint32_t>(pos & 7)), bound);
         }
     }
     return prod >> 16;
