@@ -386,3 +386,71 @@ def test_caller_workspace_is_exact_and_sufficient(n, w, p):
         shuf.shuffle_inplace_ws(t2, seed, small, sid, sp)
     assert ei.value.code == shuf.SHUF_ENOMEM
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("w", [8, 16])
+def test_full_size_2e28_wider_elements_equal_oracle(w):
+    """The width sweep at n = 2^28: u64 and 16-byte records (key = i,
+    payload = splitmix64(i)) element by element against the oracle."""
+    n = 1 << 28
+    seed = 0xDEC0DE ^ w
+    host = workloads.identity(n, w)
+    print(f"[gpu] full size n=2^28 w={w} seed={seed}", flush=True)
+    got = gpu_shuffle(host, seed, None)
+    want = oracle_shuffle(host, seed, oracle.default_params(n, w))
+    assert_same(got, want, f"2^28 w={w}")
+    if w == 16:  # no torn records: every payload still matches its key
+        assert np.array_equal(got[:, 1], workloads.splitmix64(got[:, 0]))
+
+
+def test_movers_fraction_matches_overflow_statistic():
+    """One tiled level (n just below 2^21 u32: k = 256 buckets, c = T/k = 64
+    items per piece).  The movers are the overflow items (simulated fraction
+    0.40 / sqrt(c) = 5 %) plus the placed items displaced by the shift from
+    equal to exact region boundaries; the shift at boundary b is a random
+    walk of b steps with variance n/k each, so the displaced items number at
+    most about sum_b sqrt(2 b n / (pi k)) = 0.53 k sqrt(n), 9 % here."""
+    shuf = _lib()
+    n = (1 << 21) - 12345
+    host = workloads.identity(n, 4)
+    gpu_shuffle(host, 2024, None)
+    st = shuf.last_stats()
+    assert st["tiled_levels"] == 1
+    frac = st["movers"] / n
+    assert 0.05 < frac < 0.14, frac
+
+
+def test_concurrent_host_threads_and_streams():
+    """Two host threads shuffle different arrays on two streams at the same
+    time; each result equals the same call made alone."""
+    import threading
+
+    shuf = _lib()
+    dev = _dev()
+    hosts = [workloads.random_values(3_000_000, 4, 41), workloads.random_values(2_500_000, 4, 42)]
+    tens = [to_dev(h) for h in hosts]
+    streams = [torch.cuda.Stream(device=dev) for _ in hosts]
+    errors = []
+
+    def work(i):
+        try:
+            with torch.cuda.device(dev):
+                for _ in range(3):
+                    shuf.shuffle_inplace_ex(tens[i], 900 + i, i, stream=streams[i])
+        except Exception as e:  # pragma: no cover - reported below
+            errors.append(e)
+
+    # three applications of the same permutation: compare with applying it thrice alone
+    thr = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for x in thr:
+        x.start()
+    for x in thr:
+        x.join()
+    torch.cuda.synchronize()
+    assert not errors
+    for i, h in enumerate(hosts):
+        t = to_dev(h)
+        for _ in range(3):
+            shuf.shuffle_inplace_ex(t, 900 + i, i)
+        torch.cuda.synchronize()
+        assert np.array_equal(from_dev(tens[i], h), from_dev(t, h))
