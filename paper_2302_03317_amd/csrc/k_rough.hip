@@ -23,6 +23,28 @@ namespace ipss {
 
 namespace {
 
+// A thread's R elements in registers.  16-byte elements are held as four
+// arrays of words: an array of vectors would be left in scratch memory.
+template <typename E, int R>
+struct ElemRegs {
+    E v[R];
+    __device__ __forceinline__ E get(int r) const { return v[r]; }
+    __device__ __forceinline__ void set(int r, const E& e) { v[r] = e; }
+};
+
+template <int R>
+struct ElemRegs<uint4, R> {
+    uint32_t x[R], y[R], z[R], w[R];
+    __device__ __forceinline__ uint4 get(int r) const { return make_uint4(x[r], y[r], z[r], w[r]); }
+    __device__ __forceinline__ void set(int r, const uint4& e)
+    {
+        x[r] = e.x;
+        y[r] = e.y;
+        z[r] = e.z;
+        w[r] = e.w;
+    }
+};
+
 // Stable ranks of one wave's rounds for KAPPA-bit labels.  Round r gives lane
 // l the staging slot first + 64r; pk[r] receives label | rank << 8 where rank
 // counts earlier items of the wave with the same label.
@@ -139,11 +161,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
     const uint32_t first = wv * 64u * R + lane;
     // Reads of slots past the tile's end fetch slot 0 (in bounds, unused) so
     // that the loop has no branches and its reads overlap.
-    E data[R];
+    ElemRegs<E, R> data;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t q = first + 64u * r;
-        data[r] = stage[q < ts ? q : 0u];
+        data.set(r, stage[q < ts ? q : 0u]);
     }
     __syncthreads();  // staging is free: labels and per-wave counters overlay it
 
@@ -269,7 +291,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t q = first + 64u * r;
-        if (q < ts) stage[pk[r]] = data[r];
+        if (q < ts) stage[pk[r]] = data.get(r);
     }
     __syncthreads();
 

@@ -8,9 +8,9 @@
 
 namespace ipss {
 
-struct __attribute__((aligned(16))) Elem16 {
-    uint64_t lo, hi;
-};
+// A 16-byte element, moved as one opaque vector of four words (the vector
+// type keeps per-thread element arrays in registers).
+using Elem16 = uint4;
 
 // Every kernel addresses elements through the descriptors' element
 // addresses (see elem_ptr) and keys its randomness with their seeds.
