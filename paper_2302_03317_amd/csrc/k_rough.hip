@@ -138,6 +138,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
         const uint32_t b0 = nblk[b], nb = nblk[b + 1] - b0;
         for (uint32_t j = lane; j < nb; j += 64) bpiece[b0 + j] = static_cast<uint8_t>(b);
     }
+    // The block map is complete before the loads go out: a barrier after
+    // them would wait for the loads.
+    __syncthreads();
 
     // Pieces -> staging, one contiguous run each, straight into LDS.
     {
@@ -152,8 +155,21 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
                     __builtin_amdgcn_global_load_lds(src + s0 + j + lane, dst + d0 + j, 4, 0, 0);
             }
         }
-        __builtin_amdgcn_s_waitcnt(0);
     }
+    // While the loads are in flight: the Philox blocks of this thread's label
+    // blocks (a tile touches at most T/16 + 2k <= 3 * kThreads blocks).
+    constexpr int kBlk = 3;
+    static_assert((kTileBytesMax / 4) / 16 + 2 * kKmax <= kBlk * kThreads, "label blocks per thread");
+    Word4 lw[kBlk];
+#pragma unroll
+    for (int u = 0; u < kBlk; ++u) {
+        const uint32_t i = tid + u * kThreads;
+        if (i < nblocks) {
+            const uint32_t b = bpiece[i];
+            lw[u] = label_block(key, sd.level, ((pbase + lo[b]) >> 4) + (i - nblk[b]));
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
     // Wave wv owns read-order slots [wv * 64R, (wv + 1) * 64R); round r gives
@@ -172,11 +188,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
     // Labels in staging order: block i of the tile belongs to piece
     // bpiece[i]; d is the offset of its first position from the piece start.
     const uint32_t sh = 8 - kappa;
-    for (uint32_t i = tid; i < nblocks; i += kThreads) {
+#pragma unroll
+    for (int u = 0; u < kBlk; ++u) {
+        const uint32_t i = tid + u * kThreads;
+        if (i >= nblocks) continue;
         const uint32_t b = bpiece[i];
         const uint64_t p0 = pbase + lo[b];
         const uint64_t B = (p0 >> 4) + (i - nblk[b]);
-        const Word4 v = label_block(key, sd.level, B);
+        const Word4 v = lw[u];
         const int32_t d = static_cast<int32_t>(static_cast<uint32_t>(B << 4) - static_cast<uint32_t>(p0));
         const uint32_t c = cap[b];
         const int32_t q0 = static_cast<int32_t>(qoff[b]) + d;
