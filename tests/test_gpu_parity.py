@@ -314,17 +314,19 @@ def _is_identity_permutation(t, n):
     return bool(seen.all())
 
 
-@pytest.mark.parametrize("log2n,w", [(32, 4), (31, 8)])
-def test_full_size_properties(log2n, w):
+@pytest.mark.parametrize("log2n,w,extra", [(32, 4, 0), (31, 8, 0), (32, 8, 12345)])
+def test_full_size_properties(log2n, w, extra):
     """The single-array headline sizes in the benchmark's launch
     configuration: the output is a permutation of the input, a rerun with
     the same seed gives the same bytes, another stream id does not, and the
-    number of fixed points is small (Poisson(1) for a uniform permutation)."""
+    number of fixed points is small (Poisson(1) for a uniform permutation).
+    2^32 + 12345 u64 items (32 GiB) take the 64-bit paths of the piece
+    arithmetic (tile x remainder beyond 32 bits) at a ragged size."""
     shuf = _lib()
     dev = _dev()
-    n = 1 << log2n
+    n = (1 << log2n) + extra
     dt = torch.int32 if w == 4 else torch.int64
-    print(f"[gpu] full size properties n=2^{log2n} w={w}", flush=True)
+    print(f"[gpu] full size properties n=2^{log2n}+{extra} w={w}", flush=True)
     a = torch.empty(n, dtype=dt, device=dev)
     chunk = 1 << 27
     for s in range(0, n, chunk):
