@@ -200,10 +200,33 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
         const uint32_t c = cap[b];
         const int32_t q0 = static_cast<int32_t>(qoff[b]) + d;
         if (d >= 0 && static_cast<uint32_t>(d) + 16u <= c) {
+            // a whole block inside the piece: its 16 label bytes as words
+            // (top kappa bits of every byte), stored as four aligned words,
+            // or as three byte-aligned middle words and four edge bytes
+            const uint32_t msk = 0x01010101u * (0xFFu >> sh);
+            const uint32_t L0 = (v.x >> sh) & msk, L1 = (v.y >> sh) & msk;
+            const uint32_t L2 = (v.z >> sh) & msk, L3 = (v.w >> sh) & msk;
+            const uint32_t a = static_cast<uint32_t>(q0) & 3u;
             uint8_t* out = lab + q0;
-#pragma unroll
-            for (uint32_t j = 0; j < 16; ++j)
-                out[j] = static_cast<uint8_t>(__builtin_amdgcn_ubfe(word_of(v, j >> 2), 8 * (j & 3) + sh, kappa));
+            if (a == 0) {
+                uint32_t* ow = reinterpret_cast<uint32_t*>(out);
+                ow[0] = L0;
+                ow[1] = L1;
+                ow[2] = L2;
+                ow[3] = L3;
+            } else {
+                uint32_t* ow = reinterpret_cast<uint32_t*>(out - a);  // aligned
+                const uint32_t sft = 4u - a;
+                ow[1] = __builtin_amdgcn_alignbyte(L1, L0, sft);
+                ow[2] = __builtin_amdgcn_alignbyte(L2, L1, sft);
+                ow[3] = __builtin_amdgcn_alignbyte(L3, L2, sft);
+                // bytes 0 .. 3-a of the block end the first word, bytes
+                // 16-a .. 15 begin the fifth
+                for (uint32_t j = 0; j < 4; ++j) {
+                    if (j < sft) out[j] = static_cast<uint8_t>(L0 >> (8 * j));
+                    else out[12 + j] = static_cast<uint8_t>(L3 >> (8 * j));
+                }
+            }
         } else {
 #pragma unroll
             for (uint32_t j = 0; j < 16; ++j)
