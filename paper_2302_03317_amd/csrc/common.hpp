@@ -7,8 +7,10 @@
 
 namespace ipss {
 
-constexpr int kThreads = 512;              // threads of a tile / leaf workgroup
+constexpr int kThreads = 512;              // threads of a leaf workgroup
 constexpr int kWaves = kThreads / 64;      // wave64
+constexpr int kRoughThreads = 1024;        // threads of a tile workgroup
+constexpr int kRoughWaves = kRoughThreads / 64;
 constexpr uint32_t kTileBytesMax = 65536;  // most bytes of one tile's elements
 constexpr uint32_t kKmax = 256;            // labels live in one byte
 constexpr uint32_t kChunk = 256;           // tiles per chunk of the table scans
@@ -100,8 +102,8 @@ __host__ __device__ __forceinline__ uint32_t align16(uint32_t x) { return (x + 1
 
 struct RoughLayout {
     uint32_t stage;    // T elements of staging; labels, counters and slot tables overlay it
-    uint32_t counts;   // per-wave counters: kWaves rows of (kmax + 1) u32
-    uint32_t slot_tab; // per-wave slot table: kWaves rows of kmax uint2
+    uint32_t counts;   // per-wave counters: kRoughWaves rows of (kmax + 1) u32
+    uint32_t slot_tab; // per-wave slot table: kRoughWaves rows of kmax uint2
     uint32_t tables;   // offset of the per-piece tables
     uint32_t bpiece;   // piece of every label block, one byte each
     uint32_t total;
@@ -111,8 +113,8 @@ __host__ __device__ __forceinline__ RoughLayout rough_layout(uint32_t T, uint32_
 {
     RoughLayout L;
     L.counts = align16(T);
-    L.slot_tab = L.counts + align16(kWaves * (kmax + 1) * 4u);
-    const uint32_t overlay = L.slot_tab + kWaves * kmax * 8u;
+    L.slot_tab = L.counts + align16(kRoughWaves * (kmax + 1) * 4u);
+    const uint32_t overlay = L.slot_tab + kRoughWaves * kmax * 8u;
     L.stage = align16(T * w);
     if (overlay > L.stage) L.stage = align16(overlay);
     // lo: (kmax+1) u64; qoff, cap, fill, ovt, hot, nblk: (kmax+1) u32 each; 16 u32 misc

@@ -81,7 +81,7 @@ __device__ __forceinline__ void rank_rounds(const uint8_t* lab, uint32_t* Hw, ui
 }
 
 template <typename E, int R>
-__global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict__ subs,
+__global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __restrict__ subs,
                                                     const uint32_t* __restrict__ tile_sub,
                                                     uint32_t* __restrict__ cnt_tab, Params prm)
 {
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
 
     // Pieces of this tile, their offsets in read order, and the label blocks
     // (16 positions per Philox call) each piece touches.
-    for (uint32_t b = tid; b < k; b += kThreads) {
+    for (uint32_t b = tid; b < k; b += kRoughThreads) {
         const Piece pc = piece_of(sd.m, kappa, sd.tiles, t, b);
         lo[b] = pc.lo;
         cap[b] = static_cast<uint32_t>(pc.cap);
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
     __syncthreads();
     const uint32_t ts = qoff[k];
     const uint32_t nblocks = nblk[k];
-    for (uint32_t b = wv; b < k; b += kWaves) {
+    for (uint32_t b = wv; b < k; b += kRoughWaves) {
         const uint32_t b0 = nblk[b], nb = nblk[b + 1] - b0;
         for (uint32_t j = lane; j < nb; j += 64) bpiece[b0 + j] = static_cast<uint8_t>(b);
     }
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(X);
         uint32_t* dst = reinterpret_cast<uint32_t*>(stage);
-        for (uint32_t b = wv; b < k; b += kWaves) {
+        for (uint32_t b = wv; b < k; b += kRoughWaves) {
             const uint32_t nw = cap[b] * kWordsPerElem;
             const uint64_t s0 = lo[b] * kWordsPerElem;
             const uint32_t d0 = qoff[b] * kWordsPerElem;
@@ -157,13 +157,13 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
         }
     }
     // While the loads are in flight: the Philox blocks of this thread's label
-    // blocks (a tile touches at most T/16 + 2k <= 3 * kThreads blocks).
-    constexpr int kBlk = 3;
-    static_assert((kTileBytesMax / 4) / 16 + 2 * kKmax <= kBlk * kThreads, "label blocks per thread");
+    // blocks (a tile touches at most T/16 + 2k <= 2 * kRoughThreads blocks).
+    constexpr int kBlk = 2;
+    static_assert((kTileBytesMax / 4) / 16 + 2 * kKmax <= kBlk * kRoughThreads, "label blocks per thread");
     Word4 lw[kBlk];
 #pragma unroll
     for (int u = 0; u < kBlk; ++u) {
-        const uint32_t i = tid + u * kThreads;
+        const uint32_t i = tid + u * kRoughThreads;
         if (i < nblocks) {
             const uint32_t b = bpiece[i];
             lw[u] = label_block(key, sd.level, ((pbase + lo[b]) >> 4) + (i - nblk[b]));
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
     const uint32_t sh = 8 - kappa;
 #pragma unroll
     for (int u = 0; u < kBlk; ++u) {
-        const uint32_t i = tid + u * kThreads;
+        const uint32_t i = tid + u * kRoughThreads;
         if (i >= nblocks) continue;
         const uint32_t b = bpiece[i];
         const uint64_t p0 = pbase + lo[b];
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
                         static_cast<uint8_t>(__builtin_amdgcn_ubfe(word_of(v, j >> 2), 8 * (j & 3) + sh, kappa));
         }
     }
-    for (uint32_t i = tid; i < kWaves * hs; i += kThreads) H[i] = 0;
+    for (uint32_t i = tid; i < kRoughWaves * hs; i += kRoughThreads) H[i] = 0;
     __syncthreads();
 
     uint32_t pk[R];
@@ -253,9 +253,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
     __syncthreads();
 
     // Per label: offsets of the waves, the tile's count, fill, overflow, holes.
-    for (uint32_t l = tid; l < k; l += kThreads) {
+    for (uint32_t l = tid; l < k; l += kRoughThreads) {
         uint32_t run = 0;
-        for (int w = 0; w < kWaves; ++w) {
+        for (int w = 0; w < kRoughWaves; ++w) {
             const uint32_t v = H[w * hs + l];
             H[w * hs + l] = run;
             run += v;
@@ -279,12 +279,12 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
     const uint32_t nfree = hot[k];
     const bool use_list = nfree <= prm.tile / 2;
     if (use_list) {
-        for (uint32_t b = tid; b < k; b += kThreads) {
+        for (uint32_t b = tid; b < k; b += kRoughThreads) {
             const uint32_t base = hot[b], f0 = qoff[b] + fill[b], nh = cap[b] - fill[b];
             for (uint32_t j = 0; j < nh; ++j) fs[base + j] = static_cast<uint16_t>(f0 + j);
         }
     }
-    for (uint32_t i = tid; i < kWaves * k; i += kThreads) {
+    for (uint32_t i = tid; i < kRoughWaves * k; i += kRoughThreads) {
         const uint32_t w = i >> kappa, l = i & (k - 1);
         const uint32_t h = H[w * hs + l];
         const int32_t B = static_cast<int32_t>(cap[l]) - static_cast<int32_t>(h);
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_rough(const SubDesc* __restrict
     {
         uint32_t* dst = reinterpret_cast<uint32_t*>(X);
         const uint32_t* src = reinterpret_cast<const uint32_t*>(stage);
-        for (uint32_t b = wv; b < k; b += kWaves) {
+        for (uint32_t b = wv; b < k; b += kRoughWaves) {
             const uint32_t nw = cap[b] * kWordsPerElem;
             const uint64_t d0 = lo[b] * kWordsPerElem;
             const uint32_t s0 = qoff[b] * kWordsPerElem;
@@ -354,10 +354,10 @@ template <typename E>
 hipError_t launch_rough_t(const SubDesc* subs, const uint32_t* tile_sub, uint32_t* cnt_tab,
                           uint64_t ntiles, const Params& prm, hipStream_t stream)
 {
-    constexpr int R = static_cast<int>(kTileBytesMax / (sizeof(E) * kThreads));
+    constexpr int R = static_cast<int>(kTileBytesMax / (sizeof(E) * kRoughThreads));
     const RoughLayout L = rough_layout(prm.tile, sizeof(E), 1u << prm.kmax_log2);
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_rough<E, R>), dim3(static_cast<uint32_t>(ntiles)), dim3(kThreads),
+    hipLaunchKernelGGL((k_rough<E, R>), dim3(static_cast<uint32_t>(ntiles)), dim3(kRoughThreads),
                        L.total, stream, subs, tile_sub, cnt_tab, prm);
     return hipGetLastError();
 }
@@ -377,9 +377,9 @@ hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_su
 
 hipError_t set_rough_lds_limits()
 {
-    constexpr int R4 = static_cast<int>(kTileBytesMax / (4 * kThreads));
-    constexpr int R8 = static_cast<int>(kTileBytesMax / (8 * kThreads));
-    constexpr int R16 = static_cast<int>(kTileBytesMax / (16 * kThreads));
+    constexpr int R4 = static_cast<int>(kTileBytesMax / (4 * kRoughThreads));
+    constexpr int R8 = static_cast<int>(kTileBytesMax / (8 * kRoughThreads));
+    constexpr int R16 = static_cast<int>(kTileBytesMax / (16 * kRoughThreads));
     hipError_t e;
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<uint32_t, R4>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
