@@ -167,6 +167,17 @@ __host__ __device__ __forceinline__ LeafLayout leaf_layout(uint32_t T, uint32_t 
 // ---- wave helpers (device) ----
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// The hardware hands the workgroups of a launch to the eight XCDs in turn
+// (workgroup g to XCD g mod 8), and every XCD has its own L2.  Renumbering so
+// that XCD x works through one contiguous run of the n work items keeps
+// neighbouring items -- which share the cache lines at their boundaries -- in
+// one L2 at about the same time.  A bijection of [0, n).
+__device__ __forceinline__ uint32_t xcd_order(uint32_t g, uint32_t n)
+{
+    const uint32_t x = g & 7u, j = g >> 3, q = n >> 3, rem = n & 7u;
+    return x * q + (x < rem ? x : rem) + j;
+}
+
 // number of set bits of `mask` below this lane
 __device__ __forceinline__ uint32_t bits_below(uint64_t mask)
 {

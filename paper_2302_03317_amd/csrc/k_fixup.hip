@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kTabThreads) void k_gather(E* __restrict__ ws, Leve
     __shared__ uint32_t fill[kKmax], kept[kKmax], disp[kKmax];
     __shared__ uint32_t ovt[kKmax + 1], hot[kKmax + 1], outt[kKmax + 1];
     const uint32_t tid = threadIdx.x, wv = tid >> 6;
-    const uint64_t g = blockIdx.x;
+    const uint64_t g = xcd_order(blockIdx.x, gridDim.x);
     const SubDesc sd = T.subs[T.tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
     const uint32_t k = 1u << sd.kappa;
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ w
     __shared__ uint64_t S[kKmax], Ktot[kKmax], MB[kKmax], lo[kKmax], kept_lo[kKmax], kpre[kKmax];
     __shared__ uint32_t kept[kKmax], nkt[kKmax + 1];
     const uint32_t tid = threadIdx.x, wv = tid >> 6;
-    const uint64_t g = blockIdx.x;
+    const uint64_t g = xcd_order(blockIdx.x, gridDim.x);
     const SubDesc sd = T.subs[T.tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
     const uint32_t k = 1u << sd.kappa;

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
     constexpr uint32_t kWaveSegMax = 64u * ROUNDS;  // largest segment split by one wave
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    const LeafDesc ld = leaves[blockIdx.x];
+    const LeafDesc ld = leaves[xcd_order(blockIdx.x, gridDim.x)];
     const uint32_t m = static_cast<uint32_t>(ld.m);
     const uint32_t kmax = 1u << prm.kmax_log2;
     const uint32_t hs = kmax + 1;  // row stride of the counters

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    const uint64_t g = blockIdx.x;
+    const uint64_t g = xcd_order(blockIdx.x, gridDim.x);
     const SubDesc sd = subs[tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
     const uint32_t kappa = sd.kappa, k = 1u << kappa;
