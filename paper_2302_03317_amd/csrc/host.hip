@@ -421,7 +421,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     void* p_big = nullptr;
     uint64_t ntiles = 0;
     if (!tiled.empty()) {
-        uint64_t tab = 0, nchunks = 0, chtab = 0, nbk = 0;
+        uint64_t tab = 0, nchunks = 0, chtab = 0, nbk = 0, max_chunks = 0;
         for (const HostSub& s : tiled) {
             SubDesc d{};
             d.elem_off = s.elem_off;
@@ -444,6 +444,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
             ntiles += d.tiles;
             tab += d.tiles * k;
             nchunks += nch;
+            if (nch > max_chunks) max_chunks = nch;
             chtab += nch * k;
             nbk += k;
             if (ntiles >= (1ull << 31) || nbk >= (1ull << 32)) return SHUF_EUNSUPPORTED;
@@ -503,6 +504,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
         T.ntiles = ntiles;
         T.nchunks = nchunks;
         T.nbuckets = nbk;
+        T.max_chunks = max_chunks;
         if (dry) {
             HIP_TRY(launch_count(T.subs, T.tile_sub, T.cnt, ntiles, stream));
         } else {

@@ -21,6 +21,9 @@ namespace ipss {
 namespace {
 
 constexpr int kTabThreads = 256;
+// Subproblems of more chunks than this get one wave per bucket in the
+// per-bucket reductions over chunks.
+constexpr uint64_t kWaveChunks = 16;
 
 // Per (tile, bucket): the rough piece, how much of it was filled, the part of
 // the placed front that lies inside the final region (kept), the displaced
@@ -35,11 +38,9 @@ struct Stats {
     uint64_t ov;       // did not fit the piece
 };
 
-__device__ __forceinline__ Stats tile_bucket(const SubDesc& sd, uint64_t t, uint32_t b,
-                                             uint32_t cnt, uint64_t S, uint64_t N)
+__device__ __forceinline__ Stats piece_stats(const Piece& pc, uint32_t cnt, uint64_t S, uint64_t N)
 {
     Stats st;
-    const Piece pc = piece_of(sd.m, sd.kappa, sd.tiles, t, b);
     st.lo = pc.lo;
     st.cap = pc.cap;
     st.fill = cnt < pc.cap ? cnt : pc.cap;
@@ -50,6 +51,56 @@ __device__ __forceinline__ Stats tile_bucket(const SubDesc& sd, uint64_t t, uint
     st.kept_lo = e > a ? a : pc.lo;
     st.disp = st.fill - st.kept;
     return st;
+}
+
+__device__ __forceinline__ Stats tile_bucket(const SubDesc& sd, uint64_t t, uint32_t b,
+                                             uint32_t cnt, uint64_t S, uint64_t N)
+{
+    return piece_stats(piece_of(sd.m, sd.kappa, sd.tiles, t, b), cnt, S, N);
+}
+
+// The pieces of region b in tiles t0, t0 + 1, ...: piece t of a region of len
+// items starts at t*q + floor(t*r / P) (len = q*P + r, P tiles), so from one
+// tile to the next the start advances by q, plus one where the remainder
+// t*r mod P wraps.  Divisions at the first tile only.
+struct PieceWalk {
+    uint64_t e0, q, r, P, off, rem;
+
+    __device__ __forceinline__ PieceWalk(const SubDesc& sd, uint64_t t0, uint32_t b)
+    {
+        e0 = (static_cast<uint64_t>(b) * sd.m) >> sd.kappa;
+        const uint64_t len = ((static_cast<uint64_t>(b + 1) * sd.m) >> sd.kappa) - e0;
+        P = sd.tiles;
+        q = len / P;
+        r = len - q * P;
+        off = piece_offset(t0, len, P);
+        const uint64_t tr = t0 * r;  // t0 < P and r < P, P <= 2^32
+        rem = ((tr | P) >> 32) == 0 ? static_cast<uint32_t>(tr) % static_cast<uint32_t>(P) : tr % P;
+    }
+    // the piece of the current tile; moves on to the next tile
+    __device__ __forceinline__ Piece next()
+    {
+        uint64_t nrem = rem + r, step = q;
+        if (nrem >= P) {
+            nrem -= P;
+            ++step;
+        }
+        const Piece pc{e0 + off, step};
+        off += step;
+        rem = nrem;
+        return pc;
+    }
+};
+
+// Inclusive prefix sum of 64-bit values across the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_inclusive_sum64(uint64_t v, uint32_t lane)
+{
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint64_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
 }
 
 __device__ __forceinline__ uint64_t chunk_tiles(const SubDesc& sd, uint64_t c, uint64_t* t0)
@@ -94,16 +145,40 @@ __global__ __launch_bounds__(kTabThreads) void k_bucket_count_total(LevelTables 
     T.N[gb] = run;
 }
 
-// S[b] = exclusive prefix of N over the subproblem's buckets
-__global__ void k_bucket_starts(LevelTables T)
+// The same with one wave per bucket, for levels whose subproblems span many
+// chunks (a thread per bucket would walk them one by one).
+__global__ __launch_bounds__(kTabThreads) void k_bucket_count_total_wave(LevelTables T)
+{
+    const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * (kTabThreads / 64) + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    if (gb >= T.nbuckets) return;  // the whole wave
+    const SubDesc sd = T.subs[T.bk_sub[gb]];
+    const uint32_t k = 1u << sd.kappa;
+    const uint32_t b = static_cast<uint32_t>(gb - sd.bk_off);
+    const uint64_t nc = num_chunks(sd);
+    uint64_t run = 0;
+    for (uint64_t c = lane; c < nc; c += 64) run += T.chA[sd.chtab_off + c * k + b];
+    run = wave_inclusive_sum64(run, lane);
+    if (lane == 63) T.N[gb] = run;
+}
+
+// S[b] = exclusive prefix of N over the subproblem's buckets; one wave per
+// subproblem, each lane a run of consecutive buckets.
+__global__ __launch_bounds__(64) void k_bucket_starts(LevelTables T)
 {
     const SubDesc sd = T.subs[blockIdx.x];
-    if (threadIdx.x != 0) return;
+    const uint32_t lane = threadIdx.x;
     const uint32_t k = 1u << sd.kappa;
-    uint64_t run = 0;
-    for (uint32_t b = 0; b < k; ++b) {
-        T.S[sd.bk_off + b] = run;
-        run += T.N[sd.bk_off + b];
+    const uint32_t per = (k + 63) / 64, b0 = lane * per;
+    uint64_t own = 0;
+    for (uint32_t j = 0; j < per; ++j)
+        if (b0 + j < k) own += T.N[sd.bk_off + b0 + j];
+    uint64_t run = wave_inclusive_sum64(own, lane) - own;
+    for (uint32_t j = 0; j < per; ++j) {
+        if (b0 + j < k) {
+            T.S[sd.bk_off + b0 + j] = run;
+            run += T.N[sd.bk_off + b0 + j];
+        }
     }
 }
 
@@ -119,9 +194,10 @@ __global__ __launch_bounds__(kTabThreads) void k_chunk_route_sum(LevelTables T)
     for (uint32_t b = threadIdx.x; b < k; b += kTabThreads) {
         const uint64_t S = T.S[sd.bk_off + b], N = T.N[sd.bk_off + b];
         uint64_t mv = 0, kp = 0;
+        PieceWalk pw(sd, t0, b);
         for (uint64_t i = 0; i < nt; ++i) {
             const uint64_t t = t0 + i;
-            const Stats st = tile_bucket(sd, t, b, T.cnt[sd.tab_off + t * k + b], S, N);
+            const Stats st = piece_stats(pw.next(), T.cnt[sd.tab_off + t * k + b], S, N);
             mv += st.disp + st.ov;
             kp += st.kept;
         }
@@ -150,6 +226,39 @@ __global__ __launch_bounds__(kTabThreads) void k_bucket_route_scan(LevelTables T
     }
     T.M[gb] = rm;
     T.K[gb] = rk;
+}
+
+// The same with one wave per bucket (subproblems of many chunks).
+__global__ __launch_bounds__(kTabThreads) void k_bucket_route_scan_wave(LevelTables T)
+{
+    const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * (kTabThreads / 64) + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    if (gb >= T.nbuckets) return;  // the whole wave
+    const SubDesc sd = T.subs[T.bk_sub[gb]];
+    const uint32_t k = 1u << sd.kappa;
+    const uint32_t b = static_cast<uint32_t>(gb - sd.bk_off);
+    const uint64_t nc = num_chunks(sd);
+    uint64_t rm = 0, rk = 0;
+    for (uint64_t c0 = 0; c0 < nc; c0 += 64) {
+        const uint64_t c = c0 + lane;
+        const uint64_t i = sd.chtab_off + c * k + b;
+        uint64_t vm = 0, vk = 0;
+        if (c < nc) {
+            vm = T.chA[i];
+            vk = T.chB[i];
+        }
+        const uint64_t sm = wave_inclusive_sum64(vm, lane), sk = wave_inclusive_sum64(vk, lane);
+        if (c < nc) {
+            T.chA[i] = rm + sm - vm;
+            T.chB[i] = rk + sk - vk;
+        }
+        rm += __shfl(sm, 63, 64);
+        rk += __shfl(sk, 63, 64);
+    }
+    if (lane == 0) {
+        T.M[gb] = rm;
+        T.K[gb] = rk;
+    }
 }
 
 // MB = exclusive prefix of M over all buckets of the level, in three steps:
@@ -225,10 +334,11 @@ __global__ __launch_bounds__(kTabThreads) void k_chunk_route_prefix(LevelTables 
         const uint64_t S = T.S[sd.bk_off + b], N = T.N[sd.bk_off + b];
         uint64_t rm = T.chA[sd.chtab_off + c * k + b];
         uint64_t rk = T.chB[sd.chtab_off + c * k + b];
+        PieceWalk pw(sd, t0, b);
         for (uint64_t i = 0; i < nt; ++i) {
             const uint64_t t = t0 + i;
             const uint64_t e = sd.tab_off + t * k + b;
-            const Stats st = tile_bucket(sd, t, b, T.cnt[e], S, N);
+            const Stats st = piece_stats(pw.next(), T.cnt[e], S, N);
             T.mpre[e] = rm;
             T.kpre[e] = rk;
             rm += st.disp + st.ov;
@@ -238,12 +348,19 @@ __global__ __launch_bounds__(kTabThreads) void k_chunk_route_prefix(LevelTables 
 }
 
 // ---- children of the level: leaves and subproblems that need another tiled level ----
-__global__ __launch_bounds__(kTabThreads) void k_children(LevelTables T, uint32_t tile_limit,
-                                                          LeafDesc* leaves, LeafDesc* big,
-                                                          unsigned long long* counters)
+// One atomic per list and workgroup: the waves' counts are added up in LDS.
+constexpr int kChildThreads = 1024;
+
+__global__ __launch_bounds__(kChildThreads) void k_children(LevelTables T, uint32_t tile_limit,
+                                                            LeafDesc* leaves, LeafDesc* big,
+                                                            unsigned long long* counters)
 {
-    // No early exit: every lane takes part in the wave-wide slot reservations.
-    const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * kTabThreads + threadIdx.x;
+    constexpr uint32_t kW = kChildThreads / 64;
+    __shared__ uint32_t wcnt[3][kW];
+    __shared__ unsigned long long wbase[2][kW];
+    // No early exit: every thread takes part in the barriers.
+    const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * kChildThreads + threadIdx.x;
     uint64_t n = 0;
     LeafDesc c{};
     if (gb < T.nbuckets) {
@@ -254,14 +371,35 @@ __global__ __launch_bounds__(kTabThreads) void k_children(LevelTables T, uint32_
     }
     const bool leaf = n >= 2 && n <= tile_limit;
     const bool more = n > tile_limit;
-    const uint64_t li = wave_reserve(&counters[0], leaf);
-    if (leaf) leaves[li] = c;
-    const uint64_t bi = wave_reserve(&counters[1], more);
-    if (more) big[bi] = c;
-    // leaf children hold at most tile_limit < 2^16 items: the wave's sum fits 32 bits
+    const uint64_t ml = __ballot(leaf), mb = __ballot(more);
+    // leaf children hold at most tile_limit < 2^16 items: a workgroup's sum fits 32 bits
     const uint32_t sum = wave_inclusive_sum(leaf ? static_cast<uint32_t>(n) : 0u);
-    const uint32_t total = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(sum), 63));
-    if (lane_id() == 0 && total) atomicAdd(&counters[2], static_cast<unsigned long long>(total));
+    if (lane == 63) {
+        wcnt[0][wv] = static_cast<uint32_t>(__popcll(ml));
+        wcnt[1][wv] = static_cast<uint32_t>(__popcll(mb));
+        wcnt[2][wv] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long nl = 0, nb = 0, ne = 0;
+        for (uint32_t w = 0; w < kW; ++w) {
+            wbase[0][w] = nl;
+            wbase[1][w] = nb;
+            nl += wcnt[0][w];
+            nb += wcnt[1][w];
+            ne += wcnt[2][w];
+        }
+        const unsigned long long bl = nl ? atomicAdd(&counters[0], nl) : 0ull;
+        const unsigned long long bb = nb ? atomicAdd(&counters[1], nb) : 0ull;
+        if (ne) atomicAdd(&counters[2], ne);
+        for (uint32_t w = 0; w < kW; ++w) {
+            wbase[0][w] += bl;
+            wbase[1][w] += bb;
+        }
+    }
+    __syncthreads();
+    if (leaf) leaves[wbase[0][wv] + bits_below(ml)] = c;
+    if (more) big[wbase[1][wv] + bits_below(mb)] = c;
 }
 
 // ---- gather: movers of one tile into the workspace ----
@@ -384,9 +522,14 @@ hipError_t launch_tables_sizes(const LevelTables& t, hipStream_t stream)
     if (t.ntiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_chunk_count_sum, dim3(static_cast<uint32_t>(t.nchunks)), dim3(kTabThreads),
                        0, stream, t);
-    hipLaunchKernelGGL(k_bucket_count_total,
-                       dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads - 1) / kTabThreads)),
-                       dim3(kTabThreads), 0, stream, t);
+    if (t.max_chunks > kWaveChunks)
+        hipLaunchKernelGGL(k_bucket_count_total_wave,
+                           dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads / 64 - 1) / (kTabThreads / 64))),
+                           dim3(kTabThreads), 0, stream, t);
+    else
+        hipLaunchKernelGGL(k_bucket_count_total,
+                           dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads - 1) / kTabThreads)),
+                           dim3(kTabThreads), 0, stream, t);
     hipLaunchKernelGGL(k_bucket_starts, dim3(static_cast<uint32_t>(t.nsubs)), dim3(64), 0, stream, t);
     return hipGetLastError();
 }
@@ -396,9 +539,14 @@ hipError_t launch_tables_routes(const LevelTables& t, hipStream_t stream)
     if (t.ntiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_chunk_route_sum, dim3(static_cast<uint32_t>(t.nchunks)), dim3(kTabThreads),
                        0, stream, t);
-    hipLaunchKernelGGL(k_bucket_route_scan,
-                       dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads - 1) / kTabThreads)),
-                       dim3(kTabThreads), 0, stream, t);
+    if (t.max_chunks > kWaveChunks)
+        hipLaunchKernelGGL(k_bucket_route_scan_wave,
+                           dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads / 64 - 1) / (kTabThreads / 64))),
+                           dim3(kTabThreads), 0, stream, t);
+    else
+        hipLaunchKernelGGL(k_bucket_route_scan,
+                           dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads - 1) / kTabThreads)),
+                           dim3(kTabThreads), 0, stream, t);
     const uint32_t nparts = static_cast<uint32_t>((t.nbuckets + kScanChunk - 1) / kScanChunk);
     hipLaunchKernelGGL(k_ws_chunk_sums, dim3(nparts), dim3(kTabThreads), 0, stream, t);
     hipLaunchKernelGGL(k_ws_scan_sums, dim3(1), dim3(64), 0, stream, t, nparts);
@@ -413,8 +561,8 @@ hipError_t launch_children(const LevelTables& t, uint32_t tile_limit, LeafDesc* 
 {
     if (t.nbuckets == 0) return hipSuccess;
     hipLaunchKernelGGL(k_children,
-                       dim3(static_cast<uint32_t>((t.nbuckets + kTabThreads - 1) / kTabThreads)),
-                       dim3(kTabThreads), 0, stream, t, tile_limit, leaves, big, counters);
+                       dim3(static_cast<uint32_t>((t.nbuckets + kChildThreads - 1) / kChildThreads)),
+                       dim3(kChildThreads), 0, stream, t, tile_limit, leaves, big, counters);
     return hipGetLastError();
 }
 

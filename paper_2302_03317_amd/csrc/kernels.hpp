@@ -44,6 +44,7 @@ struct LevelTables {
     uint32_t* err;              // [1] set non-zero by a kernel that finds an index out of range
     uint64_t ws_cap;            // workspace elements available to gather / scatter
     uint64_t nsubs, ntiles, nchunks, nbuckets;
+    uint64_t max_chunks;        // most chunks of one subproblem
 };
 
 constexpr uint32_t kScanChunk = 4096;  // buckets per block of the workspace scan
