@@ -229,23 +229,6 @@ __device__ __forceinline__ uint64_t match_label_bits(uint32_t l)
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-// Lanes with `take` set reserve consecutive slots of a shared counter with a
-// single atomic for the whole wave; returns the lane's slot (meaningful where
-// `take` is set).  Every active lane of the wave must call it.
-__device__ __forceinline__ uint64_t wave_reserve(unsigned long long* counter, bool take)
-{
-    const uint64_t mask = __ballot(take);
-    if (mask == 0) return 0;
-    const uint32_t leader = static_cast<uint32_t>(__builtin_ctzll(mask));
-    uint64_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(counter, static_cast<unsigned long long>(__popcll(mask)));
-    const uint32_t lo = static_cast<uint32_t>(
-        __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(base)), static_cast<int>(leader)));
-    const uint32_t hi = static_cast<uint32_t>(
-        __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(base >> 32)), static_cast<int>(leader)));
-    return ((static_cast<uint64_t>(hi) << 32) | lo) + bits_below(mask);
-}
-
 // Exclusive prefix sum of a[0..n) in place and a[n] = total; called by one
 // whole wave.
 __device__ __forceinline__ void wave_exclusive_scan(uint32_t* a, uint32_t n)

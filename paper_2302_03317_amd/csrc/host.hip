@@ -46,7 +46,10 @@ struct DevBuf {
             p = nullptr;
             cap = 0;
         }
-        size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+        // half again as much, so that the sizes of later steps and calls,
+        // which vary with the bucket sizes drawn, rarely force a regrowth
+        // (a device-wide synchronization)
+        size_t want = std::max<size_t>(bytes + bytes / 2, 4096);
         hipError_t e = hipMalloc(&p, want);
         if (e != hipSuccess) {
             p = nullptr;
@@ -159,8 +162,8 @@ struct Context {
     bool init = false;
     DevBuf subs, tile_sub, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, wsp, total, ws,
         leaves, leaves_cls, big, gfy, err, counters;
-    HostBuf h_subs, h_tile_sub, h_chunk_sub, h_bk_sub, h_total, h_leaves, h_big, h_gfy, h_err,
-        h_counters;
+    HostBuf h_subs, h_total, h_leaves, h_big, h_gfy, h_err, h_counters;
+    std::vector<SubDesc> hv_subs;  // the level's subproblems (kept to reuse its memory)
     shuf_stats_t stats{};
     // timing
     bool timing = false;
@@ -415,8 +418,8 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     }
     E.cur.clear();
 
-    std::vector<SubDesc> subs;
-    std::vector<uint32_t> tile_sub, chunk_sub, bk_sub;
+    std::vector<SubDesc>& subs = C.hv_subs;
+    subs.clear();
     LevelTables T{};
     void* p_big = nullptr;
     uint64_t ntiles = 0;
@@ -451,24 +454,18 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
             subs.push_back(d);
         }
         const uint32_t nsub = static_cast<uint32_t>(subs.size());
-        tile_sub.resize(ntiles);
-        chunk_sub.resize(nchunks);
-        bk_sub.resize(nbk);
         uint64_t level_elems = 0;
-        for (uint32_t i = 0; i < nsub; ++i) {
-            const SubDesc& d = subs[i];
-            std::fill(tile_sub.begin() + d.tile_off, tile_sub.begin() + d.tile_off + d.tiles, i);
-            const uint64_t nch = (d.tiles + kChunk - 1) / kChunk;
-            std::fill(chunk_sub.begin() + d.chunk_off, chunk_sub.begin() + d.chunk_off + nch, i);
-            std::fill(bk_sub.begin() + d.bk_off, bk_sub.begin() + d.bk_off + (1u << d.kappa), i);
-            level_elems += d.m;
-        }
+        for (const SubDesc& d : subs) level_elems += d.m;
         void *p_subs, *p_tile_sub, *p_chunk_sub, *p_bk_sub, *p_cnt, *p_mpre, *p_kpre, *p_chA, *p_chB,
             *p_N, *p_S, *p_M, *p_K, *p_MB, *p_wsp;
         HIP_TRY(upload(mem, C.subs, C.h_subs, subs, stream, &p_subs));
-        HIP_TRY(upload(mem, C.tile_sub, C.h_tile_sub, tile_sub, stream, &p_tile_sub));
-        HIP_TRY(upload(mem, C.chunk_sub, C.h_chunk_sub, chunk_sub, stream, &p_chunk_sub));
-        HIP_TRY(upload(mem, C.bk_sub, C.h_bk_sub, bk_sub, stream, &p_bk_sub));
+        // tile / chunk / bucket -> subproblem maps, built on the device
+        HIP_TRY(mem.take(C.tile_sub, ntiles * 4, &p_tile_sub));
+        HIP_TRY(mem.take(C.chunk_sub, nchunks * 4, &p_chunk_sub));
+        HIP_TRY(mem.take(C.bk_sub, nbk * 4, &p_bk_sub));
+        HIP_TRY(launch_level_maps(static_cast<const SubDesc*>(p_subs), nsub, ntiles, nchunks, nbk,
+                                  static_cast<uint32_t*>(p_tile_sub), static_cast<uint32_t*>(p_chunk_sub),
+                                  static_cast<uint32_t*>(p_bk_sub), stream));
         HIP_TRY(mem.take(C.cnt, tab * 4, &p_cnt));
         HIP_TRY(mem.take(C.mpre, tab * 8, &p_mpre));
         HIP_TRY(mem.take(C.kpre, tab * 8, &p_kpre));
@@ -541,10 +538,8 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
             for (uint64_t i = 0; i < nbig; ++i)
                 E.cur.push_back({bl[i].elem_off, bl[i].base, bl[i].m, bl[i].seed, bl[i].level,
                                  bl[i].stream_id, bl[i].owner});
-            // the device appends in no particular order; plan in address order
-            std::sort(E.cur.begin(), E.cur.end(), [](const HostSub& a, const HostSub& b) {
-                return a.elem_off != b.elem_off ? a.elem_off < b.elem_off : a.base < b.base;
-            });
+            // (the device appends in no particular order; a level's results do not
+            // depend on the order of its subproblems)
         }
         void* p_ws;
         HIP_TRY(mem.take(C.ws, std::max<uint64_t>(movers, 1) * w, &p_ws));

@@ -115,6 +115,43 @@ __device__ __forceinline__ uint64_t num_chunks(const SubDesc& sd)
     return (sd.tiles + kChunk - 1) / kChunk;
 }
 
+// ---- maps of a level: global tile / chunk / bucket -> subproblem ----
+// The last subproblem whose range starts at or before x (ranges start in
+// increasing order and none is empty).
+template <int F>
+__device__ __forceinline__ uint32_t sub_of(const SubDesc* subs, uint32_t nsub, uint64_t x)
+{
+    uint32_t lo = 0, hi = nsub;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        const uint64_t off = F == 0 ? subs[mid].tile_off : (F == 1 ? subs[mid].chunk_off : subs[mid].bk_off);
+        if (off <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kTabThreads) void k_level_maps(const SubDesc* __restrict__ subs,
+                                                            uint32_t nsub, uint64_t ntiles,
+                                                            uint64_t nchunks, uint64_t nbuckets,
+                                                            uint32_t* __restrict__ tile_sub,
+                                                            uint32_t* __restrict__ chunk_sub,
+                                                            uint32_t* __restrict__ bk_sub)
+{
+    uint64_t i = static_cast<uint64_t>(blockIdx.x) * kTabThreads + threadIdx.x;
+    if (i < ntiles) {
+        tile_sub[i] = sub_of<0>(subs, nsub, i);
+        return;
+    }
+    i -= ntiles;
+    if (i < nchunks) {
+        chunk_sub[i] = sub_of<1>(subs, nsub, i);
+        return;
+    }
+    i -= nchunks;
+    if (i < nbuckets) bk_sub[i] = sub_of<2>(subs, nsub, i);
+}
+
 // chA[chunk][b] = sum of the chunk's counts of bucket b
 __global__ __launch_bounds__(kTabThreads) void k_chunk_count_sum(LevelTables T)
 {
@@ -516,6 +553,18 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ w
 }
 
 }  // namespace
+
+hipError_t launch_level_maps(const SubDesc* subs, uint32_t nsub, uint64_t ntiles, uint64_t nchunks,
+                             uint64_t nbuckets, uint32_t* tile_sub, uint32_t* chunk_sub,
+                             uint32_t* bk_sub, hipStream_t stream)
+{
+    const uint64_t n = ntiles + nchunks + nbuckets;
+    if (n == 0 || nsub == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_level_maps, dim3(static_cast<uint32_t>((n + kTabThreads - 1) / kTabThreads)),
+                       dim3(kTabThreads), 0, stream, subs, nsub, ntiles, nchunks, nbuckets, tile_sub,
+                       chunk_sub, bk_sub);
+    return hipGetLastError();
+}
 
 hipError_t launch_tables_sizes(const LevelTables& t, hipStream_t stream)
 {

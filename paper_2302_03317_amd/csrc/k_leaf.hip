@@ -413,23 +413,47 @@ hipError_t leaf_t(const LeafDesc* leaves, const uint64_t* count, uint64_t stride
 
 // Sort leaves into the three classes (order inside a class is immaterial:
 // every leaf is finished independently).
-__global__ __launch_bounds__(256) void k_leaf_classes(const LeafDesc* __restrict__ in, uint64_t n,
-                                                       LeafDesc* __restrict__ out, uint64_t stride,
-                                                       uint32_t cap_s, uint32_t cap_m,
-                                                       unsigned long long* __restrict__ count)
+constexpr int kClassThreads = 1024;
+
+__global__ __launch_bounds__(kClassThreads) void k_leaf_classes(const LeafDesc* __restrict__ in,
+                                                                uint64_t n, LeafDesc* __restrict__ out,
+                                                                uint64_t stride, uint32_t cap_s,
+                                                                uint32_t cap_m,
+                                                                unsigned long long* __restrict__ count)
 {
-    // No early exit: every lane takes part in the wave-wide slot reservations.
-    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    // Slots are reserved with one atomic per class and workgroup: the waves'
+    // counts are added up in LDS.  No early exit: every thread takes part in
+    // the barriers.
+    constexpr uint32_t kW = kClassThreads / 64;
+    __shared__ uint32_t wcnt[3][kW];
+    __shared__ unsigned long long wbase[3][kW];
+    const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kClassThreads + threadIdx.x;
     LeafDesc d{};
     uint32_t c = 3;
     if (i < n) {
         d = in[i];
         c = d.m <= cap_s ? 0u : (d.m <= cap_m ? 1u : 2u);
     }
+    uint64_t mask[3];
+#pragma unroll
     for (uint32_t k = 0; k < 3; ++k) {
-        const uint64_t slot = wave_reserve(&count[k], c == k);
-        if (c == k) out[k * stride + slot] = d;
+        mask[k] = __ballot(c == k);
+        if (lane == 0) wcnt[k][wv] = static_cast<uint32_t>(__popcll(mask[k]));
     }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const uint32_t k = threadIdx.x;
+        unsigned long long run = 0;
+        for (uint32_t w = 0; w < kW; ++w) {
+            wbase[k][w] = run;
+            run += wcnt[k][w];
+        }
+        const unsigned long long b = run ? atomicAdd(&count[k], run) : 0ull;
+        for (uint32_t w = 0; w < kW; ++w) wbase[k][w] += b;
+    }
+    __syncthreads();
+    if (c < 3) out[c * stride + wbase[c][wv] + bits_below(mask[c])] = d;
 }
 
 template <typename E>
@@ -464,8 +488,8 @@ hipError_t launch_leaf_classes(const LeafDesc* in, uint64_t n, LeafDesc* out, ui
                                const uint32_t* caps, unsigned long long* count, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_leaf_classes, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0,
-                       stream, in, n, out, stride, caps[0], caps[1], count);
+    hipLaunchKernelGGL(k_leaf_classes, dim3(static_cast<uint32_t>((n + kClassThreads - 1) / kClassThreads)),
+                       dim3(kClassThreads), 0, stream, in, n, out, stride, caps[0], caps[1], count);
     return hipGetLastError();
 }
 

@@ -56,6 +56,12 @@ constexpr uint32_t kScanChunk = 4096;  // buckets per block of the workspace sca
 hipError_t launch_children(const LevelTables& t, uint32_t tile_limit, LeafDesc* leaves,
                            LeafDesc* big, unsigned long long* counters, hipStream_t stream);
 
+// Tile, chunk and bucket -> subproblem maps of a level (each subproblem's
+// tile_off / chunk_off / bk_off start its ranges, in increasing order).
+hipError_t launch_level_maps(const SubDesc* subs, uint32_t nsub, uint64_t ntiles, uint64_t nchunks,
+                             uint64_t nbuckets, uint32_t* tile_sub, uint32_t* chunk_sub,
+                             uint32_t* bk_sub, hipStream_t stream);
+
 // Counts -> final sizes and starts; movers, kept prefixes; workspace bases.
 hipError_t launch_tables_sizes(const LevelTables& t, hipStream_t stream);
 hipError_t launch_tables_routes(const LevelTables& t, hipStream_t stream);
