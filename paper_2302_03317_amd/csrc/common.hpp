@@ -97,6 +97,35 @@ __host__ __device__ __forceinline__ Piece piece_of(uint64_t m, uint32_t kappa, u
     return {lo, hi - lo};
 }
 
+// The pieces of tile t in all k regions of a subproblem: region b starts at
+// e0 = floor(b*m/k) and holds floor(m/k) or floor(m/k) + 1 items, so a piece's
+// offset inside its region takes one of two values per tile.  The level's
+// table holds both for every tile (pofs[2g + s] = piece_offset(t, len0 + s, P)
+// for global tile g = tile t of its subproblem); a tile reads its own pair
+// and the next tile's, and selects per region.  Same bounds as piece_of.
+struct TilePieces {
+    uint64_t m, len0, off[2][2];  // off[s][u]: offset at tile t + u for length len0 + s
+    uint32_t kappa;
+
+    __host__ __device__ __forceinline__ TilePieces(uint64_t m_, uint32_t kappa_, uint64_t P, uint64_t t,
+                                                   const uint64_t* pofs_g)
+        : m(m_), len0(m_ >> kappa_), kappa(kappa_)
+    {
+        const bool last = t + 1 >= P;  // piece_offset(P, len, P) = len
+        off[0][0] = pofs_g[0];
+        off[1][0] = pofs_g[1];
+        off[0][1] = last ? len0 : pofs_g[2];
+        off[1][1] = last ? len0 + 1 : pofs_g[3];
+    }
+    __host__ __device__ __forceinline__ Piece of(uint32_t b) const
+    {
+        const uint64_t e0 = (static_cast<uint64_t>(b) * m) >> kappa;
+        const uint64_t e1 = (static_cast<uint64_t>(b + 1) * m) >> kappa;
+        const uint32_t s = (e1 - e0) != len0 ? 1u : 0u;
+        return {e0 + off[s][0], off[s][1] - off[s][0]};
+    }
+};
+
 // LDS layout of the tile and leaf kernels (bytes).
 __host__ __device__ __forceinline__ uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 

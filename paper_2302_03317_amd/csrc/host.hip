@@ -160,7 +160,7 @@ struct Context {
     std::mutex mu;
     LeafLists lists;  // used by blocking calls (under mu)
     bool init = false;
-    DevBuf subs, tile_sub, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, wsp, total, ws,
+    DevBuf subs, tile_sub, tile_pofs, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, wsp, total, ws,
         leaves, leaves_cls, big, gfy, err, counters;
     HostBuf h_subs, h_total, h_leaves, h_big, h_gfy, h_err, h_counters;
     std::vector<SubDesc> hv_subs;  // the level's subproblems (kept to reuse its memory)
@@ -456,16 +456,18 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
         const uint32_t nsub = static_cast<uint32_t>(subs.size());
         uint64_t level_elems = 0;
         for (const SubDesc& d : subs) level_elems += d.m;
-        void *p_subs, *p_tile_sub, *p_chunk_sub, *p_bk_sub, *p_cnt, *p_mpre, *p_kpre, *p_chA, *p_chB,
+        void *p_subs, *p_tile_sub, *p_tile_pofs, *p_chunk_sub, *p_bk_sub, *p_cnt, *p_mpre, *p_kpre, *p_chA, *p_chB,
             *p_N, *p_S, *p_M, *p_K, *p_MB, *p_wsp;
         HIP_TRY(upload(mem, C.subs, C.h_subs, subs, stream, &p_subs));
         // tile / chunk / bucket -> subproblem maps, built on the device
         HIP_TRY(mem.take(C.tile_sub, ntiles * 4, &p_tile_sub));
+        HIP_TRY(mem.take(C.tile_pofs, ntiles * 16, &p_tile_pofs));
         HIP_TRY(mem.take(C.chunk_sub, nchunks * 4, &p_chunk_sub));
         HIP_TRY(mem.take(C.bk_sub, nbk * 4, &p_bk_sub));
         HIP_TRY(launch_level_maps(static_cast<const SubDesc*>(p_subs), nsub, ntiles, nchunks, nbk,
-                                  static_cast<uint32_t*>(p_tile_sub), static_cast<uint32_t*>(p_chunk_sub),
-                                  static_cast<uint32_t*>(p_bk_sub), stream));
+                                  static_cast<uint32_t*>(p_tile_sub), static_cast<uint64_t*>(p_tile_pofs),
+                                  static_cast<uint32_t*>(p_chunk_sub), static_cast<uint32_t*>(p_bk_sub),
+                                  stream));
         HIP_TRY(mem.take(C.cnt, tab * 4, &p_cnt));
         HIP_TRY(mem.take(C.mpre, tab * 8, &p_mpre));
         HIP_TRY(mem.take(C.kpre, tab * 8, &p_kpre));
@@ -482,6 +484,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
 
         T.subs = static_cast<const SubDesc*>(p_subs);
         T.tile_sub = static_cast<const uint32_t*>(p_tile_sub);
+        T.tile_pofs = static_cast<const uint64_t*>(p_tile_pofs);
         T.chunk_sub = static_cast<const uint32_t*>(p_chunk_sub);
         T.bk_sub = static_cast<const uint32_t*>(p_bk_sub);
         T.cnt = static_cast<uint32_t*>(p_cnt);
@@ -503,10 +506,10 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
         T.nbuckets = nbk;
         T.max_chunks = max_chunks;
         if (dry) {
-            HIP_TRY(launch_count(T.subs, T.tile_sub, T.cnt, ntiles, stream));
+            HIP_TRY(launch_count(T.subs, T.tile_sub, T.tile_pofs, T.cnt, ntiles, stream));
         } else {
             SpanGuard g(C, stream, 0, 2.0 * level_elems * w);
-            HIP_TRY(launch_rough(w, T.subs, T.tile_sub, T.cnt, ntiles, prm, stream));
+            HIP_TRY(launch_rough(w, T.subs, T.tile_sub, T.tile_pofs, T.cnt, ntiles, prm, stream));
         }
         {
             SpanGuard g(C, stream, 1, 0.0);

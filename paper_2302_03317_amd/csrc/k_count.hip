@@ -17,6 +17,7 @@ constexpr int kCountThreads = 256;
 
 __global__ __launch_bounds__(kCountThreads) void k_count(const SubDesc* __restrict__ subs,
                                                          const uint32_t* __restrict__ tile_sub,
+                                                         const uint64_t* __restrict__ tile_pofs,
                                                          uint32_t* __restrict__ cnt_tab)
 {
     __shared__ uint32_t hist[kKmax];
@@ -29,8 +30,9 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const SubDesc* __restri
     const uint64_t t = g - sd.tile_off;
     const uint32_t kappa = sd.kappa, k = 1u << kappa;
     const Key key = make_key(sd.seed, sd.stream_id);
+    const TilePieces tp(sd.m, kappa, sd.tiles, t, tile_pofs + 2 * g);
     for (uint32_t b = tid; b < k; b += kCountThreads) {
-        const Piece pc = piece_of(sd.m, kappa, sd.tiles, t, b);
+        const Piece pc = tp.of(b);
         const uint64_t p0 = sd.base + pc.lo;
         plo[b] = p0;
         pcap[b] = static_cast<uint32_t>(pc.cap);
@@ -57,12 +59,12 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const SubDesc* __restri
 
 }  // namespace
 
-hipError_t launch_count(const SubDesc* subs, const uint32_t* tile_sub, uint32_t* cnt_tab,
-                        uint64_t ntiles, hipStream_t stream)
+hipError_t launch_count(const SubDesc* subs, const uint32_t* tile_sub, const uint64_t* tile_pofs,
+                        uint32_t* cnt_tab, uint64_t ntiles, hipStream_t stream)
 {
     if (ntiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_count, dim3(static_cast<uint32_t>(ntiles)), dim3(kCountThreads), 0, stream,
-                       subs, tile_sub, cnt_tab);
+                       subs, tile_sub, tile_pofs, cnt_tab);
     return hipGetLastError();
 }
 

@@ -53,11 +53,6 @@ __device__ __forceinline__ Stats piece_stats(const Piece& pc, uint32_t cnt, uint
     return st;
 }
 
-__device__ __forceinline__ Stats tile_bucket(const SubDesc& sd, uint64_t t, uint32_t b,
-                                             uint32_t cnt, uint64_t S, uint64_t N)
-{
-    return piece_stats(piece_of(sd.m, sd.kappa, sd.tiles, t, b), cnt, S, N);
-}
 
 // The pieces of region b in tiles t0, t0 + 1, ...: piece t of a region of len
 // items starts at t*q + floor(t*r / P) (len = q*P + r, P tiles), so from one
@@ -135,12 +130,19 @@ __global__ __launch_bounds__(kTabThreads) void k_level_maps(const SubDesc* __res
                                                             uint32_t nsub, uint64_t ntiles,
                                                             uint64_t nchunks, uint64_t nbuckets,
                                                             uint32_t* __restrict__ tile_sub,
+                                                            uint64_t* __restrict__ tile_pofs,
                                                             uint32_t* __restrict__ chunk_sub,
                                                             uint32_t* __restrict__ bk_sub)
 {
     uint64_t i = static_cast<uint64_t>(blockIdx.x) * kTabThreads + threadIdx.x;
     if (i < ntiles) {
-        tile_sub[i] = sub_of<0>(subs, nsub, i);
+        const uint32_t j = sub_of<0>(subs, nsub, i);
+        tile_sub[i] = j;
+        // the tile's piece offsets for the two region lengths
+        const SubDesc& sd = subs[j];
+        const uint64_t t = i - sd.tile_off, len0 = sd.m >> sd.kappa;
+        tile_pofs[2 * i] = piece_offset(t, len0, sd.tiles);
+        tile_pofs[2 * i + 1] = piece_offset(t, len0 + 1, sd.tiles);
         return;
     }
     i -= ntiles;
@@ -452,10 +454,11 @@ __global__ __launch_bounds__(kTabThreads) void k_gather(E* __restrict__ ws, Leve
     const uint64_t t = g - sd.tile_off;
     const uint32_t k = 1u << sd.kappa;
     const E* X = elem_ptr<E>(sd.elem_off) + sd.base;
+    const TilePieces tp(sd.m, sd.kappa, sd.tiles, t, T.tile_pofs + 2 * g);
     for (uint32_t b = tid; b < k; b += kTabThreads) {
         const uint64_t e = sd.tab_off + t * k + b;
         const uint64_t gb = sd.bk_off + b;
-        const Stats st = tile_bucket(sd, t, b, T.cnt[e], T.S[gb], T.N[gb]);
+        const Stats st = piece_stats(tp.of(b), T.cnt[e], T.S[gb], T.N[gb]);
         lo[b] = st.lo;
         kept_lo[b] = st.kept_lo;
         fill[b] = static_cast<uint32_t>(st.fill);
@@ -508,10 +511,11 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ w
     const uint64_t t = g - sd.tile_off;
     const uint32_t k = 1u << sd.kappa;
     E* X = elem_ptr<E>(sd.elem_off) + sd.base;
+    const TilePieces tp(sd.m, sd.kappa, sd.tiles, t, T.tile_pofs + 2 * g);
     for (uint32_t b = tid; b < k; b += kTabThreads) {
         const uint64_t e = sd.tab_off + t * k + b;
         const uint64_t gb = sd.bk_off + b;
-        const Stats st = tile_bucket(sd, t, b, T.cnt[e], T.S[gb], T.N[gb]);
+        const Stats st = piece_stats(tp.of(b), T.cnt[e], T.S[gb], T.N[gb]);
         S[b] = T.S[gb];
         Ktot[b] = T.K[gb];
         MB[b] = T.MB[gb];
@@ -555,14 +559,14 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ w
 }  // namespace
 
 hipError_t launch_level_maps(const SubDesc* subs, uint32_t nsub, uint64_t ntiles, uint64_t nchunks,
-                             uint64_t nbuckets, uint32_t* tile_sub, uint32_t* chunk_sub,
-                             uint32_t* bk_sub, hipStream_t stream)
+                             uint64_t nbuckets, uint32_t* tile_sub, uint64_t* tile_pofs,
+                             uint32_t* chunk_sub, uint32_t* bk_sub, hipStream_t stream)
 {
     const uint64_t n = ntiles + nchunks + nbuckets;
     if (n == 0 || nsub == 0) return hipSuccess;
     hipLaunchKernelGGL(k_level_maps, dim3(static_cast<uint32_t>((n + kTabThreads - 1) / kTabThreads)),
                        dim3(kTabThreads), 0, stream, subs, nsub, ntiles, nchunks, nbuckets, tile_sub,
-                       chunk_sub, bk_sub);
+                       tile_pofs, chunk_sub, bk_sub);
     return hipGetLastError();
 }
 

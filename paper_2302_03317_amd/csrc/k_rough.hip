@@ -83,6 +83,7 @@ __device__ __forceinline__ void rank_rounds(const uint8_t* lab, uint32_t* Hw, ui
 template <typename E, int R>
 __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __restrict__ subs,
                                                     const uint32_t* __restrict__ tile_sub,
+                                                    const uint64_t* __restrict__ tile_pofs,
                                                     uint32_t* __restrict__ cnt_tab, Params prm)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -116,8 +117,9 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
 
     // Pieces of this tile, their offsets in read order, and the label blocks
     // (16 positions per Philox call) each piece touches.
+    const TilePieces tp(sd.m, kappa, sd.tiles, t, tile_pofs + 2 * g);
     for (uint32_t b = tid; b < k; b += kRoughThreads) {
-        const Piece pc = piece_of(sd.m, kappa, sd.tiles, t, b);
+        const Piece pc = tp.of(b);
         lo[b] = pc.lo;
         cap[b] = static_cast<uint32_t>(pc.cap);
         qoff[b] = static_cast<uint32_t>(pc.cap);
@@ -351,26 +353,27 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
 }
 
 template <typename E>
-hipError_t launch_rough_t(const SubDesc* subs, const uint32_t* tile_sub, uint32_t* cnt_tab,
-                          uint64_t ntiles, const Params& prm, hipStream_t stream)
+hipError_t launch_rough_t(const SubDesc* subs, const uint32_t* tile_sub, const uint64_t* tile_pofs,
+                          uint32_t* cnt_tab, uint64_t ntiles, const Params& prm, hipStream_t stream)
 {
     constexpr int R = static_cast<int>(kTileBytesMax / (sizeof(E) * kRoughThreads));
     const RoughLayout L = rough_layout(prm.tile, sizeof(E), 1u << prm.kmax_log2);
     if (ntiles == 0) return hipSuccess;
     hipLaunchKernelGGL((k_rough<E, R>), dim3(static_cast<uint32_t>(ntiles)), dim3(kRoughThreads),
-                       L.total, stream, subs, tile_sub, cnt_tab, prm);
+                       L.total, stream, subs, tile_sub, tile_pofs, cnt_tab, prm);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_sub,
-                        uint32_t* cnt_tab, uint64_t ntiles, const Params& prm, hipStream_t stream)
+                        const uint64_t* tile_pofs, uint32_t* cnt_tab, uint64_t ntiles,
+                        const Params& prm, hipStream_t stream)
 {
     switch (w) {
-    case 4: return launch_rough_t<uint32_t>(subs, tile_sub, cnt_tab, ntiles, prm, stream);
-    case 8: return launch_rough_t<uint64_t>(subs, tile_sub, cnt_tab, ntiles, prm, stream);
-    case 16: return launch_rough_t<Elem16>(subs, tile_sub, cnt_tab, ntiles, prm, stream);
+    case 4: return launch_rough_t<uint32_t>(subs, tile_sub, tile_pofs, cnt_tab, ntiles, prm, stream);
+    case 8: return launch_rough_t<uint64_t>(subs, tile_sub, tile_pofs, cnt_tab, ntiles, prm, stream);
+    case 16: return launch_rough_t<Elem16>(subs, tile_sub, tile_pofs, cnt_tab, ntiles, prm, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -17,16 +17,18 @@ using Elem16 = uint4;
 
 // Rough pass of one tiled level: one workgroup per tile.
 hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_sub,
-                        uint32_t* cnt_tab, uint64_t ntiles, const Params& prm, hipStream_t stream);
+                        const uint64_t* tile_pofs, uint32_t* cnt_tab, uint64_t ntiles,
+                        const Params& prm, hipStream_t stream);
 hipError_t set_rough_lds_limits();
 // The count table of one tiled level without moving elements (planning).
-hipError_t launch_count(const SubDesc* subs, const uint32_t* tile_sub, uint32_t* cnt_tab,
-                        uint64_t ntiles, hipStream_t stream);
+hipError_t launch_count(const SubDesc* subs, const uint32_t* tile_sub, const uint64_t* tile_pofs,
+                        uint32_t* cnt_tab, uint64_t ntiles, hipStream_t stream);
 
 // Device tables of one tiled level (see k_fixup.hip).
 struct LevelTables {
     const SubDesc* subs;
     const uint32_t* tile_sub;   // global tile -> subproblem
+    const uint64_t* tile_pofs;  // [tile][2] piece offsets inside a region (see TilePieces)
     const uint32_t* chunk_sub;  // global chunk -> subproblem
     const uint32_t* bk_sub;     // global bucket -> subproblem
     uint32_t* cnt;              // [tile][bucket] counts from the rough pass
@@ -57,10 +59,11 @@ hipError_t launch_children(const LevelTables& t, uint32_t tile_limit, LeafDesc* 
                            LeafDesc* big, unsigned long long* counters, hipStream_t stream);
 
 // Tile, chunk and bucket -> subproblem maps of a level (each subproblem's
-// tile_off / chunk_off / bk_off start its ranges, in increasing order).
+// tile_off / chunk_off / bk_off start its ranges, in increasing order), and
+// every tile's two piece offsets (see TilePieces).
 hipError_t launch_level_maps(const SubDesc* subs, uint32_t nsub, uint64_t ntiles, uint64_t nchunks,
-                             uint64_t nbuckets, uint32_t* tile_sub, uint32_t* chunk_sub,
-                             uint32_t* bk_sub, hipStream_t stream);
+                             uint64_t nbuckets, uint32_t* tile_sub, uint64_t* tile_pofs,
+                             uint32_t* chunk_sub, uint32_t* bk_sub, hipStream_t stream);
 
 // Counts -> final sizes and starts; movers, kept prefixes; workspace bases.
 hipError_t launch_tables_sizes(const LevelTables& t, hipStream_t stream);
