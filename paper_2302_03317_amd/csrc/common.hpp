@@ -124,6 +124,18 @@ struct TilePieces {
         const uint32_t s = (e1 - e0) != len0 ? 1u : 0u;
         return {e0 + off[s][0], off[s][1] - off[s][0]};
     }
+    // Items of the tile's pieces 0 .. b-1 (b <= k): the regions before b are
+    // b*len0 + n1 items long, n1 of them one longer, so the sum is
+    // b*c0 + n1*(c1 - c0) with c_s the piece size for length len0 + s
+    // (arithmetic mod 2^32: c1 - c0 may be -1).
+    __host__ __device__ __forceinline__ uint32_t start(uint32_t b) const
+    {
+        const uint32_t c0 = static_cast<uint32_t>(off[0][1] - off[0][0]);
+        const uint32_t c1 = static_cast<uint32_t>(off[1][1] - off[1][0]);
+        const uint32_t n1 = static_cast<uint32_t>(((static_cast<uint64_t>(b) * m) >> kappa) -
+                                                  static_cast<uint64_t>(b) * len0);
+        return b * c0 + n1 * (c1 - c0);
+    }
 };
 
 // LDS layout of the tile and leaf kernels (bytes).
@@ -194,6 +206,17 @@ __host__ __device__ __forceinline__ LeafLayout leaf_layout(uint32_t T, uint32_t 
 }
 
 // ---- wave helpers (device) ----
+// A workgroup barrier that waits only for this wave's LDS operations
+// (lgkmcnt), not for its outstanding global loads -- among them direct
+// global-to-LDS loads, which keep streaming while the workgroup works on
+// other LDS data.  The memory clobber keeps the compiler from moving memory
+// operations across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // The hardware hands the workgroups of a launch to the eight XCDs in turn

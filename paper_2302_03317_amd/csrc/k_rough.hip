@@ -87,7 +87,9 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
                                                     uint32_t* __restrict__ cnt_tab, Params prm)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    // the wave index is the same in all lanes: kept in a scalar register
+    const uint32_t wv = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(tid >> 6)));
     const uint64_t g = xcd_order(blockIdx.x, gridDim.x);
     const SubDesc sd = subs[tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
@@ -115,14 +117,34 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     const uint64_t pbase = sd.base;
     const Key key = make_key(sd.seed, sd.stream_id);
 
-    // Pieces of this tile, their offsets in read order, and the label blocks
-    // (16 positions per Philox call) each piece touches.
+    // Pieces -> staging, one contiguous run each, straight into LDS.  A
+    // piece's staging offset has a closed form (TilePieces::start), so every
+    // wave sends its pieces' loads before any table is built.
     const TilePieces tp(sd.m, kappa, sd.tiles, t, tile_pofs + 2 * g);
+    const uint32_t ts = tp.start(k);  // items of the tile
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(X);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(stage);
+        for (uint32_t b = wv; b < k; b += kRoughWaves) {
+            const Piece pc = tp.of(b);
+            const uint32_t nw = static_cast<uint32_t>(pc.cap) * kWordsPerElem;
+            const uint64_t s0 = pc.lo * kWordsPerElem;
+            const uint32_t d0 = tp.start(b) * kWordsPerElem;
+            for (uint32_t j = 0; j < nw; j += 64) {
+                if (j + lane < nw)
+                    __builtin_amdgcn_global_load_lds(src + s0 + j + lane, dst + d0 + j, 4, 0, 0);
+            }
+        }
+    }
+
+    // While the loads are in flight: the piece tables and the label blocks
+    // (16 positions per Philox call) each piece touches.  The barriers here
+    // wait for LDS operations only, not for the loads.
     for (uint32_t b = tid; b < k; b += kRoughThreads) {
         const Piece pc = tp.of(b);
         lo[b] = pc.lo;
         cap[b] = static_cast<uint32_t>(pc.cap);
-        qoff[b] = static_cast<uint32_t>(pc.cap);
+        qoff[b] = tp.start(b);
         uint32_t nb = 0;
         if (pc.cap) {
             const uint64_t p0 = pbase + pc.lo, p1 = p0 + pc.cap - 1;
@@ -130,34 +152,16 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
         }
         nblk[b] = nb;
     }
-    __syncthreads();
-    if (wv == 0) wave_exclusive_scan(qoff, k);
-    if (wv == 1) wave_exclusive_scan(nblk, k);
-    __syncthreads();
-    const uint32_t ts = qoff[k];
+    lds_barrier();
+    if (wv == 0) wave_exclusive_scan(nblk, k);
+    lds_barrier();
     const uint32_t nblocks = nblk[k];
     for (uint32_t b = wv; b < k; b += kRoughWaves) {
         const uint32_t b0 = nblk[b], nb = nblk[b + 1] - b0;
         for (uint32_t j = lane; j < nb; j += 64) bpiece[b0 + j] = static_cast<uint8_t>(b);
     }
-    // The block map is complete before the loads go out: a barrier after
-    // them would wait for the loads.
-    __syncthreads();
+    lds_barrier();
 
-    // Pieces -> staging, one contiguous run each, straight into LDS.
-    {
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(X);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(stage);
-        for (uint32_t b = wv; b < k; b += kRoughWaves) {
-            const uint32_t nw = cap[b] * kWordsPerElem;
-            const uint64_t s0 = lo[b] * kWordsPerElem;
-            const uint32_t d0 = qoff[b] * kWordsPerElem;
-            for (uint32_t j = 0; j < nw; j += 64) {
-                if (j + lane < nw)
-                    __builtin_amdgcn_global_load_lds(src + s0 + j + lane, dst + d0 + j, 4, 0, 0);
-            }
-        }
-    }
     // While the loads are in flight: the Philox blocks of this thread's label
     // blocks (a tile touches at most T/16 + 2k <= 2 * kRoughThreads blocks).
     constexpr int kBlk = 2;

@@ -1,9 +1,10 @@
 // Host-only check (no GPU): the per-tile piece offsets (two per tile, from the
 // level table) used by the tile, count and fix-up kernels give the same piece
 // bounds as the direct formula piece_of (region b = [floor(b*m/k),
-// floor((b+1)*m/k)), piece t starts at floor(t*len/P)) for random subproblem
-// sizes, bucket counts and tile counts, including sizes beyond 2^32.  Built
-// with hipcc --cuda-host-only.
+// floor((b+1)*m/k)), piece t starts at floor(t*len/P)), and the closed-form
+// staging offsets equal the running sums of the piece sizes, for random
+// subproblem sizes, bucket counts and tile counts, including sizes beyond
+// 2^32.  Built with hipcc --cuda-host-only.
 #include <cstdio>
 #include <random>
 
@@ -35,8 +36,18 @@ int main()
             const uint64_t pofs[4] = {piece_offset(t, len0, P), piece_offset(t, len0 + 1, P),
                                       piece_offset(t + 1, len0, P), piece_offset(t + 1, len0 + 1, P)};
             const TilePieces tp(m, kappa, P, t, pofs);
-            for (uint32_t b = 0; b < k; ++b) {
+            uint64_t before = 0;  // items of pieces 0 .. b-1
+            for (uint32_t b = 0; b <= k; ++b) {
+                if (tp.start(b) != static_cast<uint32_t>(before)) {
+                    std::printf("start mismatch m=%llu kappa=%u P=%llu t=%llu b=%u\n",
+                                static_cast<unsigned long long>(m), kappa,
+                                static_cast<unsigned long long>(P),
+                                static_cast<unsigned long long>(t), b);
+                    return 1;
+                }
+                if (b == k) break;
                 const Piece a = piece_of(m, kappa, P, t, b), c = tp.of(b);
+                before += a.cap;
                 if (a.lo != c.lo || a.cap != c.cap) {
                     std::printf("mismatch m=%llu kappa=%u P=%llu t=%llu b=%u\n",
                                 static_cast<unsigned long long>(m), kappa,
