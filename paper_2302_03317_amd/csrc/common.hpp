@@ -206,6 +206,13 @@ __host__ __device__ __forceinline__ LeafLayout leaf_layout(uint32_t T, uint32_t 
 }
 
 // ---- wave helpers (device) ----
+// A value known to be the same in every lane of the wave, kept in a scalar
+// register (loops and branches on it need no lane masks).
+__device__ __forceinline__ uint32_t uniform(uint32_t v)
+{
+    return static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v)));
+}
+
 // A workgroup barrier that waits only for this wave's LDS operations
 // (lgkmcnt), not for its outstanding global loads -- among them direct
 // global-to-LDS loads, which keep streaming while the workgroup works on

@@ -177,7 +177,8 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
     constexpr int EMAX = ROUNDS;
     constexpr uint32_t kWaveSegMax = 64u * ROUNDS;  // largest segment split by one wave
     extern __shared__ __align__(16) uint8_t smem[];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t wv = uniform(tid >> 6);  // the same in all lanes of a wave
     const LeafDesc ld = leaves[xcd_order(blockIdx.x, gridDim.x)];
     const uint32_t m = static_cast<uint32_t>(ld.m);
     const uint32_t kmax = 1u << prm.kmax_log2;
@@ -283,8 +284,8 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
 
         // Large segments: the whole workgroup, one segment at a time.
         for (uint32_t bi = 0; bi < nbig; ++bi) {
-            const uint32_t i = misc[4 + bi];
-            const uint32_t e = cur[i];
+            const uint32_t i = uniform(misc[4 + bi]);
+            const uint32_t e = uniform(cur[i]);
             const uint32_t s0 = seg_start(e), len = seg_len(e);
             uint32_t* out = nxt + tmpk[i];
             switch (kappa_in_tile(len, prm)) {
@@ -301,8 +302,8 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
 
         // Other splitting segments: one wave each.
         for (uint32_t j = wv; j < nwave; j += kWaves) {
-            const uint32_t i = wl[j];
-            const uint32_t e = cur[i];
+            const uint32_t i = uniform(wl[j]);
+            const uint32_t e = uniform(cur[i]);
             const uint32_t s0 = seg_start(e), len = seg_len(e);
             uint32_t* Hw = H + wv * hs;
             uint32_t* out = nxt + tmpk[i];

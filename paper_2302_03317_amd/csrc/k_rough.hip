@@ -88,8 +88,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
-    // the wave index is the same in all lanes: kept in a scalar register
-    const uint32_t wv = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(tid >> 6)));
+    const uint32_t wv = uniform(tid >> 6);  // the same in all lanes of a wave
     const uint64_t g = xcd_order(blockIdx.x, gridDim.x);
     const SubDesc sd = subs[tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
