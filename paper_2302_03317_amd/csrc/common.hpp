@@ -32,6 +32,25 @@ __host__ __device__ __forceinline__ E* elem_ptr(uint64_t elem_addr)
     return reinterpret_cast<E*>(static_cast<uintptr_t>(elem_addr * sizeof(E)));
 }
 
+// Device memory seen through the global address space: its loads and stores
+// are global instructions, not flat ones, so they do not count on the LDS
+// counter and a wait for an LDS result does not wait for them.
+// (The qualifier applies to the device pass; the host pass of the same source
+// only needs the kernels' types to exist.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using global_t = __attribute__((address_space(1))) T;
+#else
+template <typename T>
+using global_t = T;
+#endif
+
+template <typename E>
+__device__ __forceinline__ global_t<E>* elem_gptr(uint64_t elem_addr)
+{
+    return (global_t<E>*)(static_cast<uintptr_t>(elem_addr * sizeof(E)));
+}
+
 // One subproblem of the tiled regime at the current level.
 struct SubDesc {
     uint64_t elem_off;  // element address of its array's first element

@@ -453,7 +453,7 @@ __global__ __launch_bounds__(kTabThreads) void k_gather(E* __restrict__ ws, Leve
     const SubDesc sd = T.subs[T.tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
     const uint32_t k = 1u << sd.kappa;
-    const E* X = elem_ptr<E>(sd.elem_off) + sd.base;
+    const global_t<E>* X = elem_gptr<E>(sd.elem_off) + sd.base;
     const TilePieces tp(sd.m, sd.kappa, sd.tiles, t, T.tile_pofs + 2 * g);
     for (uint32_t b = tid; b < k; b += kTabThreads) {
         const uint64_t e = sd.tab_off + t * k + b;
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ w
     const SubDesc sd = T.subs[T.tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
     const uint32_t k = 1u << sd.kappa;
-    E* X = elem_ptr<E>(sd.elem_off) + sd.base;
+    global_t<E>* X = elem_gptr<E>(sd.elem_off) + sd.base;
     const TilePieces tp(sd.m, sd.kappa, sd.tiles, t, T.tile_pofs + 2 * g);
     for (uint32_t b = tid; b < k; b += kTabThreads) {
         const uint64_t e = sd.tab_off + t * k + b;

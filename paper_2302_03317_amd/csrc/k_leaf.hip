@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
     uint32_t* misc = reinterpret_cast<uint32_t*>(smem + LL.misc);
     E* stage = reinterpret_cast<E*>(smem);
 
-    E* X = elem_ptr<E>(ld.elem_off) + ld.base;
+    global_t<E>* X = elem_gptr<E>(ld.elem_off) + ld.base;
     const uint64_t pbase = ld.base;
     const Key key = make_key(ld.seed, ld.stream_id);
     // labraw holds whole label blocks; lab[x] is the label byte of position pbase + x
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
     __syncthreads();
     {
         const uint32_t nw = m * static_cast<uint32_t>(sizeof(E) / 4);
-        const uint32_t* from = reinterpret_cast<const uint32_t*>(X);
+        const global_t<uint32_t>* from = reinterpret_cast<const global_t<uint32_t>*>(X);
         uint32_t* to = reinterpret_cast<uint32_t*>(stage);
         for (uint32_t j = wv * 64u; j < nw; j += kThreads) {
             if (j + lane < nw) __builtin_amdgcn_global_load_lds(from + j + lane, to + j, 4, 0, 0);
@@ -359,7 +359,7 @@ __global__ void k_fy_global(const LeafDesc* __restrict__ items)
 {
     if (threadIdx.x != 0) return;
     const LeafDesc ld = items[blockIdx.x];
-    E* X = elem_ptr<E>(ld.elem_off) + ld.base;
+    global_t<E>* X = elem_gptr<E>(ld.elem_off) + ld.base;
     const Key key = make_key(ld.seed, ld.stream_id);
     for (uint64_t i = ld.m - 1; i >= 1; --i) {
         const uint64_t p = ld.base + i;

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     uint32_t* hot = ovt + kmax + 1;
     uint32_t* nblk = hot + kmax + 1;
 
-    E* X = elem_ptr<E>(sd.elem_off) + sd.base;
+    global_t<E>* X = elem_gptr<E>(sd.elem_off) + sd.base;
     const uint64_t pbase = sd.base;
     const Key key = make_key(sd.seed, sd.stream_id);
 
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     const TilePieces tp(sd.m, kappa, sd.tiles, t, tile_pofs + 2 * g);
     const uint32_t ts = tp.start(k);  // items of the tile
     {
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(X);
+        const global_t<uint32_t>* src = reinterpret_cast<const global_t<uint32_t>*>(X);
         uint32_t* dst = reinterpret_cast<uint32_t*>(stage);
         for (uint32_t b = wv; b < k; b += kRoughWaves) {
             const Piece pc = tp.of(b);
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     lds_barrier();
     const uint32_t nblocks = nblk[k];
     for (uint32_t b = wv; b < k; b += kRoughWaves) {
-        const uint32_t b0 = nblk[b], nb = nblk[b + 1] - b0;
+        const uint32_t b0 = uniform(nblk[b]), nb = uniform(nblk[b + 1]) - b0;
         for (uint32_t j = lane; j < nb; j += 64) bpiece[b0 + j] = static_cast<uint8_t>(b);
     }
     lds_barrier();
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
 
     // Staging -> pieces, one contiguous run each.
     {
-        uint32_t* dst = reinterpret_cast<uint32_t*>(X);
+        global_t<uint32_t>* dst = reinterpret_cast<global_t<uint32_t>*>(X);
         const uint32_t* src = reinterpret_cast<const uint32_t*>(stage);
         for (uint32_t b = wv; b < k; b += kRoughWaves) {
             const uint32_t nw = cap[b] * kWordsPerElem;
