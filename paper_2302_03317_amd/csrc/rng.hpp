@@ -24,8 +24,9 @@ __device__ __forceinline__ Word4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
         const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+        // three-way exclusive or as one three-input bit operation (0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), c3, k1, 0x96);
         c0 = n0;
         c1 = static_cast<uint32_t>(p1);
         c2 = n2;
