@@ -67,6 +67,17 @@ typedef struct {
  * output for given (inputs, n, elem_bytes, seed, stream_id, params) changes. */
 uint32_t shuffle_definition_version(void);
 
+/* How the kernels compute the stable ranks of the counting sorts on the
+ * current device (not part of the definition: both ways give the same
+ * ranks, hence the same permutation):
+ *   1  one LDS atomic add per item.  Chosen where the device serves the LDS
+ *      atomic adds of one wave instruction that hit the same address in lane
+ *      order, which a probe kernel checks at the device's first call;
+ *   0  one ballot per label bit (the probe failed, or the environment has
+ *      IPSCSHUF_RANK=ballot when the device's first call runs);
+ *  -1  no call has run on the current device yet. */
+int shuffle_rank_method(void);
+
 /* Default parameters for n elements of elem_bytes each (4, 8 or 16):
  * tile = 65536 / elem_bytes, kmax_log2 = 8, n0 = 64, lmax = 32.
  * Returns SHUF_EINVAL for a null `out` or an unsupported width. */

@@ -96,6 +96,8 @@ def lib() -> ctypes.CDLL:
         u32, u64, vp, i = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
         L.shuffle_definition_version.argtypes = []
         L.shuffle_definition_version.restype = u32
+        L.shuffle_rank_method.argtypes = []
+        L.shuffle_rank_method.restype = i
         L.shuf_default_params.argtypes = [u64, u32, ctypes.POINTER(_Params)]
         L.shuf_default_params.restype = i
         L.shuffle_inplace.argtypes = [vp, u64, u32, u64, vp]
@@ -139,6 +141,11 @@ def strerror(code: int) -> str:
 
 def definition_version() -> int:
     return int(lib().shuffle_definition_version())
+
+
+def rank_method() -> int:
+    """1: stable ranks by LDS atomics, 0: by ballots, -1: no call on this device yet."""
+    return int(lib().shuffle_rank_method())
 
 
 def default_params(n: int, elem_bytes: int) -> Params:

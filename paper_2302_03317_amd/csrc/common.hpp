@@ -21,6 +21,11 @@ struct Params {
     uint32_t kmax_log2; // largest bucket-count exponent
     uint32_t n0;        // base-case size
     uint32_t lmax;      // recursion cap
+    // How the kernels compute stable ranks (not part of the definition: both
+    // give the same ranks): 1 = one LDS atomic add per item, which needs the
+    // device to serve one wave's same-address LDS atomics in lane order
+    // (checked once per device); 0 = one ballot per label bit.
+    uint32_t rank_atomic;
 };
 
 // Elements are addressed absolutely: an array at device address A holds

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -160,6 +161,7 @@ struct Context {
     std::mutex mu;
     LeafLists lists;  // used by blocking calls (under mu)
     bool init = false;
+    bool rank_atomic = false;  // see Params::rank_atomic
     DevBuf subs, tile_sub, tile_pofs, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, wsp, total, ws,
         leaves, leaves_cls, big, gfy, err, counters;
     HostBuf h_subs, h_total, h_leaves, h_big, h_gfy, h_err, h_counters;
@@ -351,12 +353,19 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
 {
     if (E.broken) return SHUF_EHIP;
     const uint32_t w = E.w;
-    const Params& prm = E.prm;
+    Params prm = E.prm;
     if (!C.init) {
         HIP_TRY(set_rough_lds_limits());
         HIP_TRY(set_leaf_lds_limits());
+        // stable ranks by LDS atomics where the device serves them in lane
+        // order; IPSCSHUF_RANK=ballot keeps the ballot method
+        bool lane_ordered = false;
+        HIP_TRY(probe_lds_lane_order(stream, &lane_ordered));
+        const char* rank_env = std::getenv("IPSCSHUF_RANK");
+        C.rank_atomic = lane_ordered && !(rank_env && std::strcmp(rank_env, "ballot") == 0);
         C.init = true;
     }
+    prm.rank_atomic = C.rank_atomic ? 1u : 0u;
     const uint32_t kmax = 1u << prm.kmax_log2;
     const uint64_t tile_limit = prm.tile - kmax;  // subproblems up to this size finish in LDS
     const bool dry = E.dry;
@@ -644,6 +653,14 @@ using namespace ipss;
 extern "C" {
 
 uint32_t shuffle_definition_version(void) { return kDefinitionVersion; }
+
+int shuffle_rank_method(void)
+{
+    Context* C = current_context();
+    if (!C) return -1;
+    std::lock_guard<std::mutex> lock(C->mu);
+    return C->init ? (C->rank_atomic ? 1 : 0) : -1;
+}
 
 int shuf_default_params(uint64_t n, uint32_t elem_bytes, shuf_params_t* out)
 {

@@ -76,7 +76,7 @@ __device__ __forceinline__ void fy_segment(uint16_t* idx, uint32_t s0, uint32_t 
 
 // Whole-workgroup stable split of segment [s0, s0 + len) by KAPPA-bit labels;
 // children (start, length) go to out[0..k).
-template <int KAPPA, int ROUNDS>
+template <int KAPPA, int ROUNDS, bool ATOMIC>
 __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* lab, uint32_t* H,
                                                 uint32_t hs, uint32_t* out, uint32_t s0,
                                                 uint32_t len, uint32_t tid, uint32_t wv,
@@ -97,11 +97,17 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
         uint32_t v = 0;
         if (r < rounds && x < end) {
             const uint32_t l = lab[x] >> sh;
-            const uint64_t peers = match_label_bits<KAPPA>(l);
-            const uint32_t below = bits_below(peers);
-            const uint32_t old = H[wv * hs + l];
-            if (below == 0) H[wv * hs + l] = old + static_cast<uint32_t>(__popcll(peers));
-            v = static_cast<uint32_t>(idx[x]) | ((old + below) << 16);
+            uint32_t rank;
+            if (ATOMIC) {
+                rank = atomicAdd(&H[wv * hs + l], 1u);  // lane-ordered: the stable rank
+            } else {
+                const uint64_t peers = match_label_bits<KAPPA>(l);
+                const uint32_t below = bits_below(peers);
+                const uint32_t old = H[wv * hs + l];
+                if (below == 0) H[wv * hs + l] = old + static_cast<uint32_t>(__popcll(peers));
+                rank = old + below;
+            }
+            v = static_cast<uint32_t>(idx[x]) | (rank << 16);
         }
         pk[r] = v;
     }
@@ -132,7 +138,7 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
 }
 
 // One wave's stable split of segment [s0, s0 + len), len <= 64 * ROUNDS.
-template <int KAPPA, int ROUNDS>
+template <int KAPPA, int ROUNDS, bool ATOMIC>
 __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, uint32_t* Hw,
                                            uint32_t* out, uint32_t s0, uint32_t len,
                                            uint32_t lane)
@@ -148,11 +154,17 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
         uint32_t v = 0;
         if (r < rounds && x < end) {
             const uint32_t l = lab[x] >> sh;
-            const uint64_t peers = match_label_bits<KAPPA>(l);
-            const uint32_t below = bits_below(peers);
-            const uint32_t old = Hw[l];
-            if (below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
-            v = static_cast<uint32_t>(idx[x]) | ((old + below) << 16);
+            uint32_t rank;
+            if (ATOMIC) {
+                rank = atomicAdd(&Hw[l], 1u);  // lane-ordered: the stable rank
+            } else {
+                const uint64_t peers = match_label_bits<KAPPA>(l);
+                const uint32_t below = bits_below(peers);
+                const uint32_t old = Hw[l];
+                if (below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
+                rank = old + below;
+            }
+            v = static_cast<uint32_t>(idx[x]) | (rank << 16);
         }
         pk[r] = v;
     }
@@ -288,15 +300,28 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
             const uint32_t e = uniform(cur[i]);
             const uint32_t s0 = seg_start(e), len = seg_len(e);
             uint32_t* out = nxt + tmpk[i];
-            switch (kappa_in_tile(len, prm)) {
-            case 1: split_workgroup<1, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 2: split_workgroup<2, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 3: split_workgroup<3, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 4: split_workgroup<4, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 5: split_workgroup<5, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 6: split_workgroup<6, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            case 7: split_workgroup<7, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-            default: split_workgroup<8, ROUNDS>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+            if (prm.rank_atomic) {
+                switch (kappa_in_tile(len, prm)) {
+                case 1: split_workgroup<1, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 2: split_workgroup<2, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 3: split_workgroup<3, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 4: split_workgroup<4, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 5: split_workgroup<5, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 6: split_workgroup<6, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 7: split_workgroup<7, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                default: split_workgroup<8, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                }
+            } else {
+                switch (kappa_in_tile(len, prm)) {
+                case 1: split_workgroup<1, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 2: split_workgroup<2, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 3: split_workgroup<3, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 4: split_workgroup<4, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 5: split_workgroup<5, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 6: split_workgroup<6, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 7: split_workgroup<7, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                default: split_workgroup<8, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                }
             }
         }
 
@@ -307,15 +332,28 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
             const uint32_t s0 = seg_start(e), len = seg_len(e);
             uint32_t* Hw = H + wv * hs;
             uint32_t* out = nxt + tmpk[i];
-            switch (kappa_in_tile(len, prm)) {
-            case 1: split_wave<1, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
-            case 2: split_wave<2, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
-            case 3: split_wave<3, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
-            case 4: split_wave<4, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
-            case 5: split_wave<5, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
-            case 6: split_wave<6, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
-            case 7: split_wave<7, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
-            default: split_wave<8, ROUNDS>(idx, lab, Hw, out, s0, len, lane); break;
+            if (prm.rank_atomic) {
+                switch (kappa_in_tile(len, prm)) {
+                case 1: split_wave<1, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
+                case 2: split_wave<2, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
+                case 3: split_wave<3, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
+                case 4: split_wave<4, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
+                case 5: split_wave<5, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
+                case 6: split_wave<6, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
+                case 7: split_wave<7, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
+                default: split_wave<8, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
+                }
+            } else {
+                switch (kappa_in_tile(len, prm)) {
+                case 1: split_wave<1, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
+                case 2: split_wave<2, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
+                case 3: split_wave<3, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
+                case 4: split_wave<4, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
+                case 5: split_wave<5, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
+                case 6: split_wave<6, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
+                case 7: split_wave<7, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
+                default: split_wave<8, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
+                }
             }
         }
         __syncthreads();

@@ -80,6 +80,77 @@ __device__ __forceinline__ void rank_rounds(const uint8_t* lab, uint32_t* Hw, ui
     }
 }
 
+// The same ranks from one LDS atomic add per item: the adds of one wave
+// instruction that hit the same label's counter return the old counts in lane
+// order (checked on the device before this path is chosen), which is the
+// stable order.
+template <int R>
+__device__ __forceinline__ void rank_rounds_atomic(const uint8_t* lab, uint32_t* Hw, uint32_t first,
+                                                   uint32_t ts, uint32_t (&pk)[R])
+{
+    constexpr int kAhead = R < 8 ? R : 8;
+#pragma unroll
+    for (int r0 = 0; r0 < R; r0 += kAhead) {
+        uint32_t lb[kAhead];
+#pragma unroll
+        for (int i = 0; i < kAhead; ++i) {
+            const uint32_t q = first + 64u * (r0 + i);
+            lb[i] = lab[q < ts ? q : 0u];
+        }
+#pragma unroll
+        for (int i = 0; i < kAhead; ++i) {
+            const int r = r0 + i;
+            const uint32_t q = first + 64u * r;
+            uint32_t v = 0;
+            if (q < ts) {
+                const uint32_t l = lb[i];
+                v = l | (atomicAdd(&Hw[l], 1u) << 8);
+            }
+            pk[r] = v;
+        }
+    }
+}
+
+// Checks on the device that LDS atomic adds of one wave instruction that hit
+// the same address return their old values in lane order, for random label
+// patterns (1 to 256 labels, all or some lanes active); out[0] counts lanes
+// that saw any other value.
+__device__ __forceinline__ uint32_t probe_hash(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_lane_order_probe(uint32_t trials,
+                                                          unsigned long long* __restrict__ out)
+{
+    __shared__ uint32_t H[4 * 257];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    uint32_t* Hw = H + wv * 257;
+    unsigned long long bad = 0;
+    for (uint32_t t = 0; t < trials; ++t) {
+        const uint32_t h = probe_hash(0x51ED270Bu ^ probe_hash(blockIdx.x * 1000003u + t * 4u + wv));
+        const uint32_t nl = 1u << (h % 9u);
+        const uint32_t l = probe_hash(h + lane * 0x9E3779B9u) & (nl - 1u);
+        const bool active = ((h >> 8) & 3u) != 0u || (probe_hash(h ^ lane) & 1u) != 0u;
+        for (uint32_t j = lane; j < 257; j += 64) Hw[j] = 0;
+        uint32_t o = 0;
+        if (active) o = atomicAdd(&Hw[l], 1u);
+        const uint64_t act = __ballot(active);
+        uint32_t expect = 0;  // active lanes below with the same label
+        for (uint32_t j = 0; j < 64; ++j) {  // every lane takes part in the shuffles
+            const uint32_t lj = static_cast<uint32_t>(__shfl(static_cast<int>(l), static_cast<int>(j), 64));
+            if (j < lane && ((act >> j) & 1u) && lj == l) ++expect;
+        }
+        if (active && o != expect) ++bad;
+    }
+    if (bad) atomicAdd(&out[0], bad);
+}
+
 template <typename E, int R>
 __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __restrict__ subs,
                                                     const uint32_t* __restrict__ tile_sub,
@@ -245,15 +316,19 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
 
     uint32_t pk[R];
     uint32_t* Hw = H + wv * hs;
-    switch (kappa) {
-    case 1: rank_rounds<1, R>(lab, Hw, first, ts, pk); break;
-    case 2: rank_rounds<2, R>(lab, Hw, first, ts, pk); break;
-    case 3: rank_rounds<3, R>(lab, Hw, first, ts, pk); break;
-    case 4: rank_rounds<4, R>(lab, Hw, first, ts, pk); break;
-    case 5: rank_rounds<5, R>(lab, Hw, first, ts, pk); break;
-    case 6: rank_rounds<6, R>(lab, Hw, first, ts, pk); break;
-    case 7: rank_rounds<7, R>(lab, Hw, first, ts, pk); break;
-    default: rank_rounds<8, R>(lab, Hw, first, ts, pk); break;
+    if (prm.rank_atomic) {
+        rank_rounds_atomic<R>(lab, Hw, first, ts, pk);
+    } else {
+        switch (kappa) {
+        case 1: rank_rounds<1, R>(lab, Hw, first, ts, pk); break;
+        case 2: rank_rounds<2, R>(lab, Hw, first, ts, pk); break;
+        case 3: rank_rounds<3, R>(lab, Hw, first, ts, pk); break;
+        case 4: rank_rounds<4, R>(lab, Hw, first, ts, pk); break;
+        case 5: rank_rounds<5, R>(lab, Hw, first, ts, pk); break;
+        case 6: rank_rounds<6, R>(lab, Hw, first, ts, pk); break;
+        case 7: rank_rounds<7, R>(lab, Hw, first, ts, pk); break;
+        default: rank_rounds<8, R>(lab, Hw, first, ts, pk); break;
+        }
     }
     __syncthreads();
 
@@ -379,6 +454,26 @@ hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_su
     case 16: return launch_rough_t<Elem16>(subs, tile_sub, tile_pofs, cnt_tab, ntiles, prm, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t probe_lds_lane_order(hipStream_t stream, bool* lane_ordered)
+{
+    *lane_ordered = false;
+    unsigned long long* d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(unsigned long long));
+    if (e != hipSuccess) return e;
+    unsigned long long h = 1;
+    e = hipMemsetAsync(d, 0, sizeof(unsigned long long), stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_lane_order_probe, dim3(1024), dim3(256), 0, stream, 64u, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return e;
+    *lane_ordered = h == 0;
+    return hipSuccess;
 }
 
 hipError_t set_rough_lds_limits()
