@@ -52,7 +52,7 @@ TRAFFIC = {
         "read_bytes": 20.230e9,
         "write_bytes": 20.659e9,
         "sources": ["k_rough.hip", "common.hpp", "rng.hpp", "kernels.hpp"],
-        "sha256": "41b1806d3e74dce973e0b9887d5a5bc3ac1af63dd0348c521bc1ee1f1bed5932",
+        "sha256": "2da81e740b7ce8a1f0514aed7e20e8fd23bfa8b631665284b57a015f4a80f1ec",
     },
 }
 

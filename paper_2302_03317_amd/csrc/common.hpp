@@ -28,15 +28,6 @@ struct Params {
     uint32_t rank_atomic;
 };
 
-// Elements are addressed absolutely: an array at device address A holds
-// element i at element address A / w + i (arrays are aligned to w), so one
-// launch can serve arrays of any number of allocations.
-template <typename E>
-__host__ __device__ __forceinline__ E* elem_ptr(uint64_t elem_addr)
-{
-    return reinterpret_cast<E*>(static_cast<uintptr_t>(elem_addr * sizeof(E)));
-}
-
 // Device memory seen through the global address space: its loads and stores
 // are global instructions, not flat ones, so they do not count on the LDS
 // counter and a wait for an LDS result does not wait for them.
@@ -50,6 +41,9 @@ template <typename T>
 using global_t = T;
 #endif
 
+// Elements are addressed absolutely: an array at device address A holds
+// element i at element address A / w + i (arrays are aligned to w), so one
+// launch can serve arrays of any number of allocations.
 template <typename E>
 __device__ __forceinline__ global_t<E>* elem_gptr(uint64_t elem_addr)
 {

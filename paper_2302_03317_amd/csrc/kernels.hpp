@@ -13,7 +13,7 @@ namespace ipss {
 using Elem16 = uint4;
 
 // Every kernel addresses elements through the descriptors' element
-// addresses (see elem_ptr) and keys its randomness with their seeds.
+// addresses (see elem_gptr) and keys its randomness with their seeds.
 
 // Rough pass of one tiled level: one workgroup per tile.
 hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_sub,
