@@ -243,6 +243,28 @@ def test_batched_equals_many():
     assert np.array_equal(from_dev(a, host), from_dev(b, host))
 
 
+@pytest.mark.parametrize("w", [4, 8, 16])
+def test_batched_edge_sizes_all_widths(w):
+    """Empty arrays, single items, the largest array that skips the tiled
+    levels (T - KMAX) and the smallest that takes one (T - KMAX + 1), and
+    arrays of several tiles with a ragged end, packed in one batch."""
+    shuf = _lib()
+    T = 65536 // w
+    sizes = [0, 1, 2, 0, 3, 64, 65, T - 256, T - 255, 2 * T + 7, 1, 0, 3 * T + 1]
+    parts = [workloads.identity(s, w) for s in sizes]
+    host = np.concatenate(parts, axis=0)
+    offs = workloads.csr_offsets(np.array(sizes, dtype=np.uint64))
+    print(f"[gpu] batched edge sizes w={w} arrays={len(sizes)} total={host.shape[0]}", flush=True)
+    t = to_dev(host)
+    shuf.shuffle_batched(t, offs, 31337)
+    torch.cuda.synchronize()
+    got = from_dev(t, host)
+    for j, s in enumerate(sizes):
+        a, b = int(offs[j]), int(offs[j + 1])
+        want = host[a:b] if s < 2 else oracle_shuffle(host[a:b], 31337, oracle.default_params(s, w), stream_id=j)
+        assert_same(got[a:b], want, f"batched w={w} array {j} (n={s})")
+
+
 def test_session_result_same_alone_and_in_mix():
     """Continuous batching: requests join while others are in flight; every
     result equals the same request run alone (the oracle, and the GPU
