@@ -291,7 +291,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the shuffle runs on one GPU (no multi-GPU path); --gpus {args.gpus} is not supported",
               file=sys.stderr)
         return 2
 
