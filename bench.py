@@ -103,6 +103,32 @@ def checksum(t, torch):
     return s1 % (1 << 64), s2 % (1 << 64)
 
 
+# The paper's own measurements (a CPU implementation; it reports no GPU
+# numbers and gives absolute rates only in its figures): hardware context,
+# not a target and not a baseline of this metric.
+PAPER_CONTEXT = {
+    "machine": "AMD EPYC 7702P, 64 cores / 128 threads, 512 GB RAM (Sec. 5)",
+    "elements": "64-bit integers",
+    "parallel_speedup_over_fastest_sequential": "up to 16x at 10 GiB and more (Sec. 5.4)",
+    "self_speedup_100GiB": 32.2,
+    "speedup_over_fisher_yates_100GiB": 142,
+    "rough_scatter_share_of_first_level": "over 90 % for n >= 2^27, 99 % for n >= 2^33 (Sec. 5.6)",
+}
+
+
+def host_description() -> str:
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs visible"
+
+
 def cpu_baseline(log2n: int, w: int) -> dict:
     """The CPU oracle (single thread) on a bounded sample of the workload."""
     import numpy as np
@@ -122,6 +148,7 @@ def cpu_baseline(log2n: int, w: int) -> dict:
         "kind": "oracle",
         "sample": f"one shuffle of 2^{log2n} {w}-byte identity elements, default parameters, "
                   f"{dt:.1f} s on one host core",
+        "host": host_description(),
     }
 
 
@@ -419,6 +446,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(min(args.cpu_sample_log2, log2n), w)
         line["cpu_fisher_yates"] = cpu_fisher_yates(min(args.cpu_sample_log2, log2n), w)
+    line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
     return 0 if before == after else 1
 
