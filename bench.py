@@ -107,12 +107,12 @@ def checksum(t, torch):
 # numbers and gives absolute rates only in its figures): hardware context,
 # not a target and not a baseline of this metric.
 PAPER_CONTEXT = {
-    "machine": "AMD EPYC 7702P, 64 cores / 128 threads, 512 GB RAM (Sec. 5)",
+    "machine": "AMD EPYC 7702P, 64 cores / 128 threads, 512 GB RAM (Sec. 6)",
     "elements": "64-bit integers",
-    "parallel_speedup_over_fastest_sequential": "up to 16x at 10 GiB and more (Sec. 5.4)",
+    "parallel_speedup_over_fastest_sequential": "up to 16x at 10 GiB and more (Sec. 6.4)",
     "self_speedup_100GiB": 32.2,
     "speedup_over_fisher_yates_100GiB": 142,
-    "rough_scatter_share_of_first_level": "over 90 % for n >= 2^27, 99 % for n >= 2^33 (Sec. 5.6)",
+    "rough_scatter_share_of_first_level": "over 90 % for n >= 2^27, 99 % for n >= 2^33 (Sec. 6.6)",
 }
 
 

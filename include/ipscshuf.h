@@ -7,11 +7,11 @@
  *   - ScatterShuffle (Sec. 2.2, Sec. 3.1): every element gets a uniform random
  *     bucket, buckets become contiguous regions, every region is shuffled
  *     recursively, and Fisher-Yates (Fig. 1) finishes small regions;
- *   - one recursion level is RoughScatter (Sec. 3.2) with each tile owning a
+ *   - one recursion level is RoughScatter (Sec. 3.3) with each tile owning a
  *     piece of every bucket (Sec. 4.1), followed by the fix-up that
- *     FineScatter performs (Sec. 3.3);
+ *     FineScatter performs (Sec. 3.4);
  *   - the permutation is reproducible from the seed and independent of
- *     scheduling (Sec. 4): every random draw is a Philox4x32-10 output keyed by
+ *     scheduling (Sec. 5): every random draw is a Philox4x32-10 output keyed by
  *     (seed, stream id, recursion level, position).
  *
  * The exact permutation is fixed by definition version 1 (see
@@ -64,12 +64,20 @@ typedef struct {
 } shuf_params_t;
 
 /* Version of the permutation definition implemented; changes whenever the
- * output for given (inputs, n, elem_bytes, seed, stream_id, params) changes. */
+ * output for given (inputs, n, elem_bytes, seed, stream_id, params) changes.
+ * Version 1 is one fixed rendition of IpScShuf (Sec. 3.2, Fig. 2): per level
+ * RoughScatter into equal regions with one piece of every region per tile
+ * (Sec. 3.3, Sec. 4.1), the exact label counts as final bucket sizes and a
+ * deterministic routing of the remaining items (the role of FineScatter,
+ * Sec. 3.4), recursion on every bucket (Sec. 3.5) and Fisher-Yates below the
+ * base-case size (Fig. 1). */
 uint32_t shuffle_definition_version(void);
 
 /* How the kernels compute the stable ranks of the counting sorts on the
- * current device (not part of the definition: both ways give the same
- * ranks, hence the same permutation):
+ * current device.  A rank is the number of earlier items of a tile with the
+ * same label, i.e. the order in which RoughScatter (Sec. 3.3) would place
+ * them; it is not part of the definition: both ways give the same ranks,
+ * hence the same permutation:
  *   1  one LDS atomic add per item.  Chosen where the device serves the LDS
  *      atomic adds of one wave instruction that hit the same address in lane
  *      order, which a probe kernel checks at the device's first call;
@@ -79,12 +87,18 @@ uint32_t shuffle_definition_version(void);
 int shuffle_rank_method(void);
 
 /* Default parameters for n elements of elem_bytes each (4, 8 or 16):
- * tile = 65536 / elem_bytes, kmax_log2 = 8, n0 = 64, lmax = 32.
+ * tile = 65536 / elem_bytes, kmax_log2 = 8, n0 = 64, lmax = 32.  The paper
+ * keeps k at most 256 (Sec. 3.1) and tunes k and the base-case size by hand
+ * (Sec. 5); here k per level follows from n and these parameters.
+ *   n     unused (the defaults do not depend on it)
+ *   out   receives the parameters; caller-owned
  * Returns SHUF_EINVAL for a null `out` or an unsupported width. */
 int shuf_default_params(uint64_t n, uint32_t elem_bytes, shuf_params_t* out);
 
 /* Shuffle n elements of elem_bytes (4, 8 or 16) bytes at device pointer ptr
- * in place, with stream id 0 and the default parameters.
+ * in place, with stream id 0 and the default parameters: a uniformly random
+ * permutation (Sec. 2.2) by the in-place ScatterShuffle (IpScShuf, Sec. 3.2,
+ * Fig. 2), parallelised per level over tiles (Sec. 4.1).
  *   ptr         device pointer, aligned to elem_bytes; may be NULL if n <= 1
  *   n           element count, n < 2^40
  *   elem_bytes  4, 8 or 16; elements are moved as opaque words of that size
@@ -95,14 +109,20 @@ int shuffle_inplace(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, v
 
 /* As shuffle_inplace with an explicit stream id (the fourth Philox counter
  * word; distinct ids give independent permutations for one seed) and explicit
- * parameters.  `params` must not be NULL.  Additional errors: SHUF_EINVAL for
+ * parameters.  Every random draw is a pure function of (seed, stream id,
+ * level, position), the GPU form of Sec. 5's reproducible subtask
+ * generators; the pool supplies the workspace (see shuffle_inplace_ws for a
+ * caller-supplied one).  `params` must not be NULL.  Additional errors: SHUF_EINVAL for
  * parameters outside the ranges above, SHUF_EUNSUPPORTED when the parameters
  * need more LDS than one workgroup has. */
 int shuffle_inplace_ex(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed,
                        uint32_t stream_id, const shuf_params_t* params, void* stream);
 
 /* Exact device workspace, in bytes, that shuffle_inplace_ws needs for these
- * arguments (the permutation's recursion depends on the seed and stream id,
+ * arguments.  The workspace holds the items a level routes after its rough
+ * pass (the remainder FineScatter handles, Sec. 3.4; about 5 % of a level)
+ * and the level's tables; the paper's sequential version needs only O(k)
+ * words per level instead (Sec. 3.5).  The size is exact (the permutation's recursion depends on the seed and stream id,
  * not on the data).  It runs the planning part of the shuffle on the device
  * (labels counted per tile, the level tables) without touching any element,
  * using the library's own memory; it takes some of the time of a shuffle.
@@ -111,8 +131,9 @@ int shuffle_inplace_ex(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed
 int shuffle_workspace_bytes(uint64_t n, uint32_t elem_bytes, uint64_t seed, uint32_t stream_id,
                             const shuf_params_t* params, uint64_t* out_bytes, void* stream);
 
-/* As shuffle_inplace_ex, with every per-level device buffer (the movers of a
- * level and all level tables) carved from the caller's `workspace` of
+/* As shuffle_inplace_ex (same passages), with every per-level device buffer
+ * (the movers of a level and all level tables) carved from the caller's
+ * `workspace` of
  * `workspace_bytes` bytes, 256-byte aligned, owned by the caller and not
  * touched after the call returns.  The library still keeps its leaf lists
  * (48 bytes per finished subproblem) and pinned staging in its own pools.
@@ -126,7 +147,8 @@ int shuffle_inplace_ws(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed
                        uint64_t workspace_bytes, void* stream);
 
 /* Shuffle `count` independent arrays packed back to back at ptr, each in
- * place.  Array j occupies elements [offsets[j], offsets[j+1]) and is shuffled
+ * place: many independent shuffles run concurrently, the setting of
+ * Sec. 6.3, here in shared launches instead of one task per array.  Array j occupies elements [offsets[j], offsets[j+1]) and is shuffled
  * exactly as shuffle_inplace_ex(ptr + offsets[j] * elem_bytes,
  * offsets[j+1] - offsets[j], elem_bytes, seed, j, default params).  All arrays
  * are processed together, level by level, in shared launches.
@@ -149,7 +171,7 @@ typedef struct {
 } shuf_array_t;
 
 /* Shuffle `count` independent arrays, each in place and anywhere in device
- * memory: array j is shuffled exactly as shuffle_inplace_ex(arrays[j].ptr,
+ * memory (independent shuffles run together, as in Sec. 6.3): array j is shuffled exactly as shuffle_inplace_ex(arrays[j].ptr,
  * arrays[j].n, elem_bytes, arrays[j].seed, arrays[j].stream_id, default
  * params).  All arrays are processed together, level by level, in shared
  * launches.  Arrays must not overlap.  `arrays` is a HOST array.
@@ -157,7 +179,9 @@ typedef struct {
  * misaligned ptr with n > 1), SHUF_EUNSUPPORTED, SHUF_ENOMEM, SHUF_EHIP. */
 int shuffle_many(const shuf_array_t* arrays, uint64_t count, uint32_t elem_bytes, void* stream);
 
-/* Continuous batching.  A session accepts shuffle requests at any time and
+/* Continuous batching (a serving loop; no passage of the paper describes
+ * one: each request is the single-array shuffle above, Sec. 3.2 and 4.1).
+ * A session accepts shuffle requests at any time and
  * advances all of them together, one step per call: a step gives every
  * in-flight request's pending subproblems one recursion level in shared
  * launches and finishes every pending subproblem that fits a tile.  Requests
@@ -191,11 +215,20 @@ int shuf_session_step(shuf_session_t* s, void* stream, uint64_t* done, uint64_t 
 int shuf_session_inflight(const shuf_session_t* s, uint64_t* inflight, uint64_t* completed_unread);
 int shuf_session_destroy(shuf_session_t* s);
 
-/* Human-readable text of an error code (static storage). */
+/* Free the device pools, pinned host staging and timing events the library
+ * keeps between calls, on every device it has used (no passage; resource
+ * management).  Waits for each such device first.  Later calls allocate them
+ * again.  It also runs by itself at process exit, before the HIP runtime is
+ * torn down.  Sessions keep their own memory until shuf_session_destroy.
+ * Must not overlap other calls of the library.  Returns SHUF_OK. */
+int shuffle_release(void);
+
+/* Human-readable text of an error code (static storage; no passage). */
 const char* shuffle_strerror(int code);
 
 /* Statistics of the most recent successful call on the calling thread's
- * current device: levels run through the tiled pass, tiles launched, mover
+ * current device (instrumentation; the mover count is the remainder that
+ * Sec. 3.3 bounds and Sec. 3.4 assigns): levels run through the tiled pass, tiles launched, mover
  * elements routed through the workspace, subproblems finished in LDS, and
  * peak workspace bytes.  For tests and benchmarks; returns SHUF_EINVAL for a
  * NULL pointer. */
@@ -210,8 +243,8 @@ typedef struct {
 } shuf_stats_t;
 int shuffle_last_stats(shuf_stats_t* out);
 
-/* Per-kernel timing with HIP events recorded on the caller's stream around
- * every launch group (instrumentation for benchmarks; it adds one event pair
+/* Per-kernel timing (instrumentation, no passage) with HIP events recorded
+ * on the caller's stream around every launch group (instrumentation for benchmarks; it adds one event pair
  * per launch).  Kinds, in this order: 0 rough pass, 1 level tables,
  * 2 fix-up gather, 3 fix-up scatter, 4 LDS leaves, 5 sequential fallback.
  * `bytes` is the algorithmic HBM traffic of the launches: every element the

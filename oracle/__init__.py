@@ -33,7 +33,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-Wall", "-Wextra", "-o", tmp, _SRC]
+            ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-Wall", "-Wextra", "-pthread", "-o", tmp, _SRC]
         )
         os.replace(tmp, _LIB)
     return _LIB
@@ -59,6 +59,31 @@ class _CParams(ctypes.Structure):
         ("n0", ctypes.c_uint32),
         ("lmax", ctypes.c_uint32),
     ]
+
+
+class _CRng(ctypes.Structure):
+    pass
+
+
+_LABEL_FN = ctypes.CFUNCTYPE(ctypes.c_uint32, ctypes.POINTER(_CRng), ctypes.c_uint32, ctypes.c_uint64,
+                             ctypes.c_uint32)
+_DRAW_FN = ctypes.CFUNCTYPE(ctypes.c_uint64, ctypes.POINTER(_CRng), ctypes.c_uint32, ctypes.c_uint64,
+                            ctypes.c_uint64)
+_CRng._fields_ = [
+    ("label", _LABEL_FN),
+    ("draw", _DRAW_FN),
+    ("seed", ctypes.c_uint64),
+    ("stream_id", ctypes.c_uint32),
+    ("ctx", ctypes.c_void_p),
+]
+
+
+def _crng(label_fn, draw_fn) -> tuple:
+    """A randomness provider whose labels and draws come from Python
+    callables label_fn(level, pos, kappa) and draw_fn(level, pos, bound)."""
+    lf = _LABEL_FN(lambda _s, level, pos, kappa: int(label_fn(level, pos, kappa)))
+    df = _DRAW_FN(lambda _s, level, pos, bound: int(draw_fn(level, pos, bound)))
+    return _CRng(lf, df, 0, 0, None), (lf, df)
 
 
 def _cparams(p: Params) -> _CParams:
@@ -94,6 +119,12 @@ def lib():
         L.css_level.restype = ctypes.c_int
         L.css_shuffle.argtypes = [vp, u64, u32, u64, u32, ctypes.POINTER(_CParams)]
         L.css_shuffle.restype = ctypes.c_int
+        L.css_shuffle_mt.argtypes = [vp, u64, u32, u64, u32, ctypes.POINTER(_CParams), u32]
+        L.css_shuffle_mt.restype = ctypes.c_int
+        L.css_shuffle_rng.argtypes = [vp, u64, u32, ctypes.POINTER(_CRng), ctypes.POINTER(_CParams)]
+        L.css_shuffle_rng.restype = ctypes.c_int
+        L.css_fy_dest.argtypes = [ctypes.POINTER(_CRng), u32, u64, u64, vp]
+        L.css_fy_dest.restype = ctypes.c_int
         L.css_fisher_yates.argtypes = [vp, u64, u32, u64, u32]
         L.css_fisher_yates.restype = ctypes.c_int
         L.css_enumerate.argtypes = [u32, ctypes.POINTER(_CParams), vp, ctypes.POINTER(u64)]
@@ -171,15 +202,42 @@ def level_dest(labels, kappa_: int, tile: int, hbm_regime: bool) -> np.ndarray:
     return dest
 
 
-def shuffle(arr: np.ndarray, seed: int, p: Params, stream_id: int = 0) -> np.ndarray:
-    """Shuffle a contiguous numpy array in place (element = one row's bytes)."""
+def shuffle(arr: np.ndarray, seed: int, p: Params, stream_id: int = 0, threads: int = 1) -> np.ndarray:
+    """Shuffle a contiguous numpy array in place (element = one row's bytes).
+
+    threads > 1 computes the top level's labels and solves its independent
+    buckets on that many host threads; the result does not depend on it."""
     if not arr.flags.c_contiguous:
         raise ValueError("array must be C-contiguous")
     n = arr.shape[0] if arr.ndim else 0
     w = arr.itemsize * (int(np.prod(arr.shape[1:])) if arr.ndim > 1 else 1)
     cp = _cparams(p)
-    _check(lib().css_shuffle(arr.ctypes.data, n, w, seed, stream_id, ctypes.byref(cp)), "css_shuffle")
+    _check(lib().css_shuffle_mt(arr.ctypes.data, n, w, seed, stream_id, ctypes.byref(cp), max(1, threads)),
+           "css_shuffle_mt")
     return arr
+
+
+def shuffle_scripted(arr: np.ndarray, p: Params, label_fn, draw_fn) -> np.ndarray:
+    """The oracle's shuffle with labels and draws supplied by Python callables
+    label_fn(level, pos, kappa) and draw_fn(level, pos, bound) (for hand-worked
+    examples); in place on a contiguous array."""
+    n = arr.shape[0]
+    w = arr.itemsize * (int(np.prod(arr.shape[1:])) if arr.ndim > 1 else 1)
+    rng, keep = _crng(label_fn, draw_fn)
+    cp = _cparams(p)
+    _check(lib().css_shuffle_rng(arr.ctypes.data, n, w, ctypes.byref(rng), ctypes.byref(cp)), "css_shuffle_rng")
+    del keep
+    return arr
+
+
+def fy_dest_scripted(m: int, level: int, base: int, draw_fn) -> np.ndarray:
+    """Fisher-Yates destination map of m items at (level, absolute start
+    `base`) with draws from draw_fn(level, pos, bound)."""
+    dest = np.zeros(max(m, 1), dtype=np.uint64)
+    rng, keep = _crng(lambda *_: 0, draw_fn)
+    _check(lib().css_fy_dest(ctypes.byref(rng), level, base, m, dest.ctypes.data), "css_fy_dest")
+    del keep
+    return dest[:m]
 
 
 def fisher_yates(arr: np.ndarray, seed: int, stream_id: int = 0) -> np.ndarray:

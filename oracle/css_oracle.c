@@ -10,19 +10,19 @@
  *     independent uniform bucket label in [0, k); the subproblem is rearranged
  *     so that bucket b occupies one contiguous region; each region is shuffled
  *     recursively; small subproblems finish with Fisher-Yates (Fig. 1, Sec. 2.2).
- *   - IpSc = RoughScatter + FineScatter (Sec. 3.2-3.3): the subproblem is cut
+ *   - IpSc = RoughScatter + FineScatter (Sec. 3.2-3.4): the subproblem is cut
  *     into k equal regions, each bucket region holds a "placed" front and a
  *     "staged" rest; most items are placed directly, the few remaining ones are
  *     assigned afterwards.
  *   - ParRoughScatter (Sec. 4.1): every parallel worker owns one piece of every
  *     bucket; here a "tile" owns piece t of each of the k equal regions.
- *   - FineScatter's role (Sec. 3.3): final bucket sizes are the exact label
+ *   - FineScatter's role (Sec. 3.4): final bucket sizes are the exact label
  *     counts, bucket boundaries move from the equal split to the exact split,
  *     and the items not yet in their final region are routed into the free
  *     positions of it.
  *   - Sampling (Sec. 2.3): k = 2^kappa so a label is a shift of random bits;
  *     bounded integers for Fisher-Yates use Lemire's multiply-and-reject.
- *   - Reproducibility (Sec. 4 "Implementation"): randomness is a pure function
+ *   - Reproducibility (Sec. 5 "Implementation"): randomness is a pure function
  *     of (seed, stream, level, position) via the Philox4x32-10 counter-based
  *     generator, so the result does not depend on scheduling.
  *
@@ -32,6 +32,7 @@
  */
 #include "css_oracle.h"
 
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -180,7 +181,7 @@ static uint64_t philox_draw_cb(css_rng_t* self, uint32_t level, uint64_t pos, ui
 /* ------------------------------------------------------------------------ */
 /* Parameters and the bucket-count schedule.
  *
- * The paper tunes k (64 or 256) and the base-case size by hand (Sec. 4
+ * The paper tunes k (64 or 256) and the base-case size by hand (Sec. 5
  * "Implementation").  Here k = 2^kappa is chosen per subproblem: with target
  * child size G (half a tile while the subproblem needs the tiled pass, half
  * the base-case size once it fits one tile), r is the number of label bits
@@ -226,8 +227,16 @@ static uint64_t piece_start(uint64_t t, uint64_t len, uint64_t P)
     return (uint64_t)(((unsigned __int128)t * len) / P);
 }
 
+/* Where one level sends its items: the item at relative position x goes to
+ * relative position y.  css_level records a destination map; the recursion
+ * copies the element straight into the level's output buffer. */
+typedef struct {
+    void (*put)(void* ctx, uint64_t x, uint64_t y);
+    void* ctx;
+} sink_t;
+
 static int exact_level(const uint8_t* labels, uint64_t m, uint64_t k, const uint64_t* S,
-                       uint64_t* dest)
+                       sink_t out)
 {
     /* Every bucket occupies exactly its final region; items keep their
      * relative order inside a bucket (a stable counting sort by label). */
@@ -235,17 +244,36 @@ static int exact_level(const uint8_t* labels, uint64_t m, uint64_t k, const uint
     if (!cnt) return CSS_ENOMEM;
     for (uint64_t i = 0; i < m; ++i) {
         uint32_t l = labels[i];
-        dest[i] = S[l] + cnt[l]++;
+        out.put(out.ctx, i, S[l] + cnt[l]++);
     }
     free(cnt);
     return CSS_OK;
 }
 
+/* A growable list of positions (the movers of one bucket). */
+typedef struct {
+    uint64_t* v;
+    uint64_t n, cap;
+} poslist_t;
+
+static int poslist_push(poslist_t* a, uint64_t x)
+{
+    if (a->n == a->cap) {
+        uint64_t ncap = a->cap ? 2 * a->cap : 64;
+        uint64_t* nv = realloc(a->v, ncap * sizeof(uint64_t));
+        if (!nv) return CSS_ENOMEM;
+        a->v = nv;
+        a->cap = ncap;
+    }
+    a->v[a->n++] = x;
+    return CSS_OK;
+}
+
 static int rough_level(const uint8_t* labels, uint64_t m, uint64_t k, uint64_t tile,
-                       const uint64_t* N, const uint64_t* S, uint64_t* dest)
+                       const uint64_t* N, const uint64_t* S, sink_t out)
 {
     /* RoughScatter over P tiles.  The subproblem is cut into k equal regions
-     * E_b = [e_b, e_{b+1}), e_b = floor(b*m/k) (Sec. 3.2: k buckets of equal
+     * E_b = [e_b, e_{b+1}), e_b = floor(b*m/k) (Sec. 3.3: k buckets of equal
      * size up to rounding).  Region E_b is cut into P pieces; tile t owns
      * piece t of every region (Sec. 4.1: each subtask gets a piece of every
      * bucket).  P is the smallest tile count with at most T items per tile. */
@@ -255,10 +283,9 @@ static int rough_level(const uint8_t* labels, uint64_t m, uint64_t k, uint64_t t
     uint64_t* lo_t = malloc(k * sizeof(uint64_t));   /* piece start, this tile */
     uint64_t* cap_t = malloc(k * sizeof(uint64_t));  /* piece length, this tile */
     uint8_t* keeper = calloc(m ? m : 1, 1);          /* by destination position */
-    uint64_t* movers = malloc((m ? m : 1) * sizeof(uint64_t));
-    uint64_t* nmov = calloc(k, sizeof(uint64_t));
+    poslist_t* movers = calloc(k, sizeof(poslist_t)); /* per bucket, in order */
     int rc = CSS_OK;
-    if (!e || !cnt || !lo_t || !cap_t || !keeper || !movers || !nmov) {
+    if (!e || !cnt || !lo_t || !cap_t || !keeper || !movers) {
         rc = CSS_ENOMEM;
         goto out;
     }
@@ -280,11 +307,11 @@ static int rough_level(const uint8_t* labels, uint64_t m, uint64_t k, uint64_t t
                 uint64_t r = cnt[l]++;
                 if (r < cap_t[l]) {
                     /* placed at the front of the tile's piece of region E_l
-                     * (Sec. 3.2: placed items sit at the front of a bucket) */
+                     * (Sec. 3.3: placed items sit at the front of a bucket) */
                     uint64_t y = lo_t[l] + r;
                     if (y >= S[l] && y < S[l] + N[l]) {
                         /* inside the final region of bucket l: stays */
-                        dest[x] = y;
+                        out.put(out.ctx, x, y);
                         keeper[y] = 1;
                         continue;
                     }
@@ -293,27 +320,45 @@ static int rough_level(const uint8_t* labels, uint64_t m, uint64_t k, uint64_t t
                  * outside the final region once the boundaries move: the item
                  * is a mover.  Movers of a bucket are kept in tile order, then
                  * read order. */
-                movers[S[l] + nmov[l]++] = x;
+                rc = poslist_push(&movers[l], x);
+                if (rc != CSS_OK) goto out;
             }
         }
     }
-    /* FineScatter's role: bucket b's final region F_b = [S_b, S_b + N_b)
-     * holds its kept items; its remaining positions, in ascending order,
-     * take the movers of bucket b in order. */
+    /* FineScatter's role (Sec. 3.4): bucket b's final region
+     * F_b = [S_b, S_b + N_b) holds its kept items; its remaining positions,
+     * in ascending order, take the movers of bucket b in order. */
     for (uint64_t b = 0; b < k; ++b) {
         uint64_t j = 0;
         for (uint64_t y = S[b]; y < S[b] + N[b]; ++y) {
             if (keeper[y]) continue;
-            if (j >= nmov[b]) { rc = CSS_EINVAL; goto out; }
-            dest[movers[S[b] + j]] = y;
+            if (j >= movers[b].n) { rc = CSS_EINVAL; goto out; }
+            out.put(out.ctx, movers[b].v[j], y);
             j++;
         }
-        if (j != nmov[b]) { rc = CSS_EINVAL; goto out; }
+        if (j != movers[b].n) { rc = CSS_EINVAL; goto out; }
     }
 out:
-    free(e); free(cnt); free(lo_t); free(cap_t); free(keeper); free(movers); free(nmov);
+    if (movers)
+        for (uint64_t b = 0; b < k; ++b) free(movers[b].v);
+    free(e); free(cnt); free(lo_t); free(cap_t); free(keeper); free(movers);
     return rc;
 }
+
+/* One level with given labels and counts N (k entries). */
+static int level_to(const uint8_t* labels, uint64_t m, uint64_t k, uint64_t tile, int hbm_regime,
+                    const uint64_t* N, sink_t out)
+{
+    uint64_t* S = calloc(k, sizeof(uint64_t));
+    if (!S) return CSS_ENOMEM;
+    for (uint64_t b = 1; b < k; ++b) S[b] = S[b - 1] + N[b - 1];
+    int rc = hbm_regime ? rough_level(labels, m, k, tile, N, S, out)
+                        : exact_level(labels, m, k, S, out);
+    free(S);
+    return rc;
+}
+
+static void put_dest(void* ctx, uint64_t x, uint64_t y) { ((uint64_t*)ctx)[x] = y; }
 
 int css_level(const uint8_t* labels, uint64_t m, uint32_t kappa, uint64_t tile,
               int hbm_regime, uint64_t* dest)
@@ -322,17 +367,14 @@ int css_level(const uint8_t* labels, uint64_t m, uint32_t kappa, uint64_t tile,
     uint64_t k = UINT64_C(1) << kappa;
     if (hbm_regime && tile <= k) return CSS_EINVAL;
     uint64_t* N = calloc(k, sizeof(uint64_t));
-    uint64_t* S = calloc(k, sizeof(uint64_t));
-    if (!N || !S) { free(N); free(S); return CSS_ENOMEM; }
+    if (!N) return CSS_ENOMEM;
     for (uint64_t i = 0; i < m; ++i) {
-        if (labels[i] >= k) { free(N); free(S); return CSS_EINVAL; }
+        if (labels[i] >= k) { free(N); return CSS_EINVAL; }
         N[labels[i]]++;
     }
-    for (uint64_t b = 1; b < k; ++b) S[b] = S[b - 1] + N[b - 1];
-    int rc = hbm_regime ? rough_level(labels, m, k, tile, N, S, dest)
-                        : exact_level(labels, m, k, S, dest);
+    sink_t out = {put_dest, dest};
+    int rc = level_to(labels, m, k, tile, hbm_regime, N, out);
     free(N);
-    free(S);
     return rc;
 }
 
@@ -358,8 +400,12 @@ int css_fy_dest(css_rng_t* rng, uint32_t level, uint64_t base, uint64_t m, uint6
 }
 
 /* ------------------------------------------------------------------------ */
-/* The recursion (Fig. 2 / Theorem 1, Sec. 3.4): IpSc on the subproblem,
- * then recurse on every bucket; Fisher-Yates at the base case. */
+/* The recursion (Fig. 2 and Theorem 1; Sec. 3.5): IpSc on the subproblem,
+ * then recurse on every bucket; Fisher-Yates at the base case.  The buckets
+ * of one level are independent subproblems (Sec. 4: after one IpSc level the
+ * k subproblems can be processed in parallel), so the top level may hand its
+ * buckets to host threads; every bucket is still solved by the same plain
+ * solve(), and the result does not depend on the number of threads. */
 
 typedef struct {
     uint8_t* data;
@@ -368,54 +414,178 @@ typedef struct {
     const css_params_t* p;
 } solve_ctx_t;
 
-static int apply_dest(solve_ctx_t* c, uint64_t base, uint64_t m, const uint64_t* dest)
+typedef struct {
+    const uint8_t* src;
+    uint8_t* dst;
+    uint32_t w;
+} copy_ctx_t;
+
+static void put_elem(void* ctx, uint64_t x, uint64_t y)
 {
-    uint8_t* tmp = malloc((m ? m : 1) * c->w);
-    if (!tmp) return CSS_ENOMEM;
-    uint8_t* a = c->data + base * c->w;
-    for (uint64_t i = 0; i < m; ++i) memcpy(tmp + dest[i] * c->w, a + i * c->w, c->w);
-    memcpy(a, tmp, m * c->w);
-    free(tmp);
-    return CSS_OK;
+    copy_ctx_t* c = ctx;
+    memcpy(c->dst + y * c->w, c->src + x * c->w, c->w);
 }
 
-static int solve(solve_ctx_t* c, uint64_t base, uint64_t m, uint32_t level)
+/* Labels of positions base + [i0, i1) at `level`, counted into N. */
+static void label_range(css_rng_t* rng, uint32_t level, uint64_t base, uint64_t i0, uint64_t i1,
+                        uint32_t kappa, uint8_t* labels, uint64_t* N)
+{
+    for (uint64_t i = i0; i < i1; ++i) {
+        labels[i] = (uint8_t)rng->label(rng, level, base + i, kappa);
+        N[labels[i]]++;
+    }
+}
+
+typedef struct {
+    css_rng_t* rng;
+    uint32_t level, kappa;
+    uint64_t base, i0, i1;
+    uint8_t* labels;
+    uint64_t N[256];
+} label_job_t;
+
+static void* label_job(void* arg)
+{
+    label_job_t* j = arg;
+    label_range(j->rng, j->level, j->base, j->i0, j->i1, j->kappa, j->labels, j->N);
+    return NULL;
+}
+
+/* Labels of the whole subproblem, split over `threads` host threads. */
+static int label_all(css_rng_t* rng, uint32_t level, uint64_t base, uint64_t m, uint32_t kappa,
+                     uint32_t threads, uint8_t* labels, uint64_t* N)
+{
+    uint64_t k = UINT64_C(1) << kappa;
+    if (threads <= 1 || m < (UINT64_C(1) << 20)) {
+        label_range(rng, level, base, 0, m, kappa, labels, N);
+        return CSS_OK;
+    }
+    label_job_t* jobs = calloc(threads, sizeof(label_job_t));
+    pthread_t* tid = calloc(threads, sizeof(pthread_t));
+    if (!jobs || !tid) { free(jobs); free(tid); return CSS_ENOMEM; }
+    uint32_t started = 0;
+    int rc = CSS_OK;
+    for (uint32_t t = 0; t < threads; ++t) {
+        jobs[t] = (label_job_t){rng, level, kappa, base, m * t / threads, m * (t + 1) / threads,
+                                labels, {0}};
+        if (pthread_create(&tid[t], NULL, label_job, &jobs[t]) != 0) { rc = CSS_ENOMEM; break; }
+        started++;
+    }
+    for (uint32_t t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+    if (rc == CSS_OK)
+        for (uint32_t t = 0; t < threads; ++t)
+            for (uint64_t b = 0; b < k; ++b) N[b] += jobs[t].N[b];
+    free(jobs);
+    free(tid);
+    return rc;
+}
+
+static int solve(solve_ctx_t* c, uint64_t base, uint64_t m, uint32_t level, uint32_t threads);
+
+/* Fisher-Yates base case on [base, base + m). */
+static int solve_fy(solve_ctx_t* c, uint64_t base, uint64_t m, uint32_t level)
+{
+    uint64_t* dest = malloc(m * sizeof(uint64_t));
+    uint8_t* tmp = malloc(m * c->w);
+    int rc = (dest && tmp) ? CSS_OK : CSS_ENOMEM;
+    if (rc == CSS_OK) rc = css_fy_dest(c->rng, level, base, m, dest);
+    if (rc == CSS_OK) {
+        uint8_t* a = c->data + base * c->w;
+        for (uint64_t i = 0; i < m; ++i) memcpy(tmp + dest[i] * c->w, a + i * c->w, c->w);
+        memcpy(a, tmp, m * c->w);
+    }
+    free(dest);
+    free(tmp);
+    return rc;
+}
+
+typedef struct {
+    solve_ctx_t* c;
+    const uint64_t* start;  /* bucket starts */
+    const uint64_t* N;      /* bucket sizes */
+    uint64_t k;
+    uint32_t level;
+    uint64_t next;          /* next bucket to take, under mu */
+    int rc;
+    pthread_mutex_t mu;
+} bucket_pool_t;
+
+static void* bucket_worker(void* arg)
+{
+    bucket_pool_t* bp = arg;
+    for (;;) {
+        pthread_mutex_lock(&bp->mu);
+        uint64_t b = bp->next++;
+        int stop = bp->rc != CSS_OK;
+        pthread_mutex_unlock(&bp->mu);
+        if (stop || b >= bp->k) return NULL;
+        int rc = solve(bp->c, bp->start[b], bp->N[b], bp->level, 1);
+        if (rc != CSS_OK) {
+            pthread_mutex_lock(&bp->mu);
+            if (bp->rc == CSS_OK) bp->rc = rc;
+            pthread_mutex_unlock(&bp->mu);
+        }
+    }
+}
+
+/* The k children of a level, in order on one thread or taken from a shared
+ * counter by `threads` host threads. */
+static int solve_children(solve_ctx_t* c, uint64_t base, const uint64_t* N, uint64_t k,
+                          uint32_t level, uint32_t threads)
+{
+    uint64_t* start = malloc(k * sizeof(uint64_t));
+    if (!start) return CSS_ENOMEM;
+    uint64_t s = base;
+    for (uint64_t b = 0; b < k; ++b) {
+        start[b] = s;
+        s += N[b];
+    }
+    int rc = CSS_OK;
+    if (threads <= 1) {
+        for (uint64_t b = 0; b < k && rc == CSS_OK; ++b) rc = solve(c, start[b], N[b], level, 1);
+        free(start);
+        return rc;
+    }
+    bucket_pool_t bp = {c, start, N, k, level, 0, CSS_OK, PTHREAD_MUTEX_INITIALIZER};
+    pthread_t* tid = calloc(threads, sizeof(pthread_t));
+    uint32_t started = 0;
+    if (tid)
+        for (uint32_t t = 0; t < threads; ++t) {
+            if (pthread_create(&tid[t], NULL, bucket_worker, &bp) != 0) break;
+            started++;
+        }
+    if (started == 0) bucket_worker(&bp);  /* no thread could start: do it here */
+    for (uint32_t t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+    free(tid);
+    free(start);
+    return bp.rc;
+}
+
+static int solve(solve_ctx_t* c, uint64_t base, uint64_t m, uint32_t level, uint32_t threads)
 {
     const css_params_t* p = c->p;
     if (m <= 1) return CSS_OK;
-    if (m <= p->n0 || level >= p->lmax) {
-        uint64_t* dest = malloc(m * sizeof(uint64_t));
-        if (!dest) return CSS_ENOMEM;
-        int rc = css_fy_dest(c->rng, level, base, m, dest);
-        if (rc == CSS_OK) rc = apply_dest(c, base, m, dest);
-        free(dest);
-        return rc;
-    }
+    if (m <= p->n0 || level >= p->lmax) return solve_fy(c, base, m, level);
     uint64_t kmax = UINT64_C(1) << p->kmax_log2;
     int hbm = m > p->tile - kmax;
     uint32_t kappa = css_kappa(m, hbm, p);
     uint64_t k = UINT64_C(1) << kappa;
 
     uint8_t* labels = malloc(m);
-    uint64_t* dest = malloc(m * sizeof(uint64_t));
+    uint8_t* out = malloc(m * c->w);
     uint64_t* N = calloc(k, sizeof(uint64_t));
-    if (!labels || !dest || !N) {
-        free(labels); free(dest); free(N);
-        return CSS_ENOMEM;
+    int rc = (labels && out && N) ? CSS_OK : CSS_ENOMEM;
+    if (rc == CSS_OK) rc = label_all(c->rng, level, base, m, kappa, threads, labels, N);
+    if (rc == CSS_OK) {
+        uint8_t* a = c->data + base * c->w;
+        copy_ctx_t cc = {a, out, c->w};
+        sink_t sink = {put_elem, &cc};
+        rc = level_to(labels, m, k, p->tile, hbm, N, sink);
+        if (rc == CSS_OK) memcpy(a, out, m * c->w);
     }
-    for (uint64_t i = 0; i < m; ++i) {
-        labels[i] = (uint8_t)c->rng->label(c->rng, level, base + i, kappa);
-        N[labels[i]]++;
-    }
-    int rc = css_level(labels, m, kappa, p->tile, hbm, dest);
-    if (rc == CSS_OK) rc = apply_dest(c, base, m, dest);
     free(labels);
-    free(dest);
-    uint64_t start = base;
-    for (uint64_t b = 0; b < k && rc == CSS_OK; ++b) {
-        rc = solve(c, start, N[b], level + 1);
-        start += N[b];
-    }
+    free(out);
+    if (rc == CSS_OK) rc = solve_children(c, base, N, k, level + 1, threads);
     free(N);
     return rc;
 }
@@ -426,14 +596,24 @@ int css_shuffle_rng(void* data, uint64_t n, uint32_t w, css_rng_t* rng, const cs
     if (rc != CSS_OK) return rc;
     if (w == 0 || (!data && n > 0)) return CSS_EINVAL;
     solve_ctx_t c = {(uint8_t*)data, w, rng, p};
-    return solve(&c, 0, n, 0);
+    return solve(&c, 0, n, 0, 1);
 }
 
 int css_shuffle(void* data, uint64_t n, uint32_t w, uint64_t seed, uint32_t stream_id,
                 const css_params_t* p)
 {
+    return css_shuffle_mt(data, n, w, seed, stream_id, p, 1);
+}
+
+int css_shuffle_mt(void* data, uint64_t n, uint32_t w, uint64_t seed, uint32_t stream_id,
+                   const css_params_t* p, uint32_t threads)
+{
+    int rc = css_check_params(p);
+    if (rc != CSS_OK) return rc;
+    if (w == 0 || (!data && n > 0)) return CSS_EINVAL;
     css_rng_t rng = {philox_label_cb, philox_draw_cb, seed, stream_id, NULL};
-    return css_shuffle_rng(data, n, w, &rng, p);
+    solve_ctx_t c = {(uint8_t*)data, w, &rng, p};
+    return solve(&c, 0, n, 0, threads ? threads : 1);
 }
 
 int css_fisher_yates(void* data, uint64_t n, uint32_t w, uint64_t seed, uint32_t stream_id)

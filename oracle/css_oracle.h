@@ -92,6 +92,12 @@ int css_fy_dest(css_rng_t* rng, uint32_t level, uint64_t base, uint64_t m, uint6
 int css_shuffle(void* data, uint64_t n, uint32_t w, uint64_t seed, uint32_t stream_id,
                 const css_params_t* p);
 
+/* The same shuffle with the independent buckets of the top level solved on
+ * `threads` host threads (and its labels computed on them); the result is
+ * identical for every thread count. */
+int css_shuffle_mt(void* data, uint64_t n, uint32_t w, uint64_t seed, uint32_t stream_id,
+                   const css_params_t* p, uint32_t threads);
+
 /* Whole shuffle with an arbitrary provider. */
 int css_shuffle_rng(void* data, uint64_t n, uint32_t w, css_rng_t* rng, const css_params_t* p);
 

@@ -28,7 +28,7 @@ def philox4x32_10(ctr, key):
 
 class PhiloxSource:
     """Labels and Fisher-Yates draws as pure functions of
-    (seed, stream, level, position) -- Sec. 4's reproducibility requirement."""
+    (seed, stream, level, position) -- Sec. 5's reproducibility requirement."""
 
     def __init__(self, seed: int, stream_id: int = 0):
         self.key = (seed & MASK32, (seed >> 32) & MASK32)
@@ -96,7 +96,7 @@ def level_dest(labels, k: int, tile: int, hbm: bool):
             seen[a] += 1
         return dest
 
-    # RoughScatter on k equal regions, one piece of each per tile (Sec. 3.2, 4.1)
+    # RoughScatter on k equal regions, one piece of each per tile (Sec. 3.3, 4.1)
     tiles = -(-m // (tile - k))
     edge = [b * m // k for b in range(k + 1)]
 

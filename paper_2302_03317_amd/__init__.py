@@ -11,6 +11,7 @@ RoughScatter and a FineScatter-style fix-up, recursing to Fisher-Yates.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -131,8 +132,19 @@ def lib() -> ctypes.CDLL:
         L.shuffle_timing_enable.restype = i
         L.shuffle_timing_read.argtypes = [ctypes.POINTER(_KernelTime)]
         L.shuffle_timing_read.restype = i
+        L.shuffle_release.argtypes = []
+        L.shuffle_release.restype = i
         _lib = L
+        # free the library's pools while the HIP runtime and torch are still up
+        atexit.register(release)
     return _lib
+
+
+def release() -> None:
+    """Free the library's device pools, pinned staging and timing events
+    (they are allocated again by the next call)."""
+    if _lib is not None:
+        _lib.shuffle_release()
 
 
 def strerror(code: int) -> str:

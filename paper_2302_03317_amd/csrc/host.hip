@@ -1,6 +1,6 @@
 // Host planner and C ABI of the in-place ScatterShuffle.
 //
-// The recursion of arXiv 2302.03317 (Fig. 2, Theorem 1) is flattened into
+// The recursion of arXiv 2302.03317 (Fig. 2; Sec. 3.5, Theorem 1) is flattened into
 // steps: in one step every waiting subproblem that needs the tiled pass gets
 // one level (one shared rough-pass launch, one set of table kernels, one
 // fix-up) and every waiting subproblem that fits a tile is finished in LDS
@@ -229,6 +229,43 @@ void collect_spans(Context& C)
 constexpr int kMaxDevices = 64;
 Context g_ctx[kMaxDevices];
 
+// Frees every device pool, pinned staging buffer and timing event the library
+// holds, on every device it has used (later calls allocate them again).  Runs
+// at process exit as well (registered once at the first call), so that none of
+// it outlives the HIP runtime or a profiler attached to it.
+void release_all()
+{
+    bool any = false;  // no HIP call at all unless a device was used
+    for (int d = 0; d < kMaxDevices; ++d) {
+        std::lock_guard<std::mutex> lock(g_ctx[d].mu);
+        any = any || g_ctx[d].init;
+    }
+    if (!any) return;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+    for (int d = 0; d < kMaxDevices; ++d) {
+        Context& C = g_ctx[d];
+        std::lock_guard<std::mutex> lock(C.mu);
+        if (!C.init) continue;
+        if (hipSetDevice(d) != hipSuccess) continue;
+        (void)hipDeviceSynchronize();
+        for (DevBuf* b : {&C.subs, &C.tile_sub, &C.tile_pofs, &C.chunk_sub, &C.bk_sub, &C.cnt, &C.mpre,
+                          &C.kpre, &C.chA, &C.chB, &C.N, &C.S, &C.M, &C.K, &C.MB, &C.wsp, &C.total,
+                          &C.ws, &C.leaves, &C.leaves_cls, &C.big, &C.gfy, &C.err, &C.counters})
+            b->release();
+        for (HostBuf* h : {&C.h_subs, &C.h_total, &C.h_leaves, &C.h_big, &C.h_gfy, &C.h_err, &C.h_counters})
+            h->release();
+        C.lists.release();
+        for (hipEvent_t e : C.event_pool) (void)hipEventDestroy(e);
+        C.event_pool.clear();
+        C.spans.clear();
+        C.events_used = 0;
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+}
+
+std::once_flag g_exit_hook;
+
 struct HostSub {
     uint64_t elem_off, base, m, seed;
     uint32_t level, stream_id, owner;
@@ -364,6 +401,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
         const char* rank_env = std::getenv("IPSCSHUF_RANK");
         C.rank_atomic = lane_ordered && !(rank_env && std::strcmp(rank_env, "ballot") == 0);
         C.init = true;
+        std::call_once(g_exit_hook, [] { std::atexit(release_all); });
     }
     prm.rank_atomic = C.rank_atomic ? 1u : 0u;
     const uint32_t kmax = 1u << prm.kmax_log2;
@@ -905,6 +943,12 @@ int shuffle_timing_read(shuf_kernel_time_t* out)
     Context& C = *Cp;
     std::lock_guard<std::mutex> lock(C.mu);
     for (int i = 0; i < SHUF_KERNEL_KINDS; ++i) out[i] = C.times[i];
+    return SHUF_OK;
+}
+
+int shuffle_release(void)
+{
+    release_all();
     return SHUF_OK;
 }
 

@@ -1,5 +1,5 @@
 // Planning pass of a tiled level: the per-(tile, bucket) label counts that
-// the rough pass (RoughScatter, arXiv 2302.03317 Sec. 3.2 and 4.1) would
+// the rough pass (RoughScatter, arXiv 2302.03317 Sec. 3.3 and 4.1) would
 // write, without moving any element.  With the level tables built from them
 // it gives the exact sizes of every level, hence a call's exact workspace.
 #include "common.hpp"

@@ -1,4 +1,4 @@
-// Fix-up of a tiled level (the role of FineScatter, arXiv 2302.03317 Sec. 3.3).
+// Fix-up of a tiled level (the role of FineScatter, arXiv 2302.03317 Sec. 3.4).
 //
 // After the rough pass every tile has written its per-bucket counts.  From
 // them the final bucket sizes N_b and starts S_b follow, so the bucket

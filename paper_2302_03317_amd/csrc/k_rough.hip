@@ -1,4 +1,4 @@
-// Rough pass of a tiled level (RoughScatter, arXiv 2302.03317 Sec. 3.2 and
+// Rough pass of a tiled level (RoughScatter, arXiv 2302.03317 Sec. 3.3 and
 // Sec. 4.1): one workgroup per tile.  Tile t of a subproblem owns piece t of
 // every one of the k equal regions.  It reads its pieces in order (piece of
 // bucket 0 first, ascending positions inside a piece), gives every item its

@@ -2,7 +2,7 @@
 // with (block, tag, stream) in the counter, so every label and every
 // Fisher-Yates draw is a pure function of (seed, stream, level, position) and
 // the permutation does not depend on how the GPU schedules the work
-// (arXiv 2302.03317, Sec. 4: reproducible subtask generators).
+// (arXiv 2302.03317, Sec. 5: reproducible subtask generators).
 #pragma once
 
 #include <hip/hip_runtime.h>

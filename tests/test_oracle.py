@@ -254,6 +254,74 @@ def test_enumeration_exercises_movers():
     assert moved > 5
 
 
+def _fig1():
+    with open(os.path.join(HERE, "golden", "fisher_yates_fig1.json")) as fh:
+        return json.load(fh)
+
+
+def test_fisher_yates_fig1_step_order_golden():
+    """Fig. 1 worked by hand (tests/golden/fisher_yates_fig1.json): the draws
+    are requested for i = m-1 down to 1 with bound i + 1, each keyed by the
+    absolute position base + i, and the swaps give the hand-derived map."""
+    g = _fig1()["single"]
+    table = {int(k): v for k, v in g["draws_by_position"].items()}
+    calls = []
+
+    def draw(level, pos, bound):
+        calls.append([level, pos, bound])
+        return table.get(pos, 0)
+
+    dest = oracle.fy_dest_scripted(g["m"], g["level"], g["base"], draw)
+    assert calls == g["calls"]
+    assert dest.tolist() == g["dest"]
+
+
+def test_fisher_yates_absolute_position_keys_golden():
+    """Two equal-size Fisher-Yates leaves at one level (hand-worked): every
+    draw is keyed by its absolute position, so the two leaves take different
+    draws; both renditions of the definition reproduce the hand result."""
+    g = _fig1()["two_leaves"]
+    p = oracle.Params(**g["params"])
+    labels = g["labels_level0"]
+    draws = {int(k): v for k, v in g["draws_level1_by_position"].items()}
+    for rendition in ("c", "spec"):
+        calls, bad = [], []
+
+        def label(level, pos, kappa):
+            if level != 0 or kappa != 1 or not 0 <= pos < len(labels):
+                bad.append((level, pos, kappa))
+                return 0
+            return labels[pos]
+
+        def draw(level, pos, bound):
+            calls.append([level, pos, bound])
+            return draws.get(pos, 0)
+
+        if rendition == "c":
+            arr = np.arange(g["n"], dtype=np.uint32)
+            oracle.shuffle_scripted(arr, p, label, draw)
+            out = arr.tolist()
+        else:
+            src = type("Scripted", (), {"label": staticmethod(label), "draw": staticmethod(draw)})
+            out = spec.shuffle(list(range(g["n"])), src, p.tile, p.kmax_log2, p.n0, p.lmax)
+        assert not bad, (rendition, bad)
+        assert calls == g["calls_level1"], rendition
+        assert out == g["result"], rendition
+
+
+def test_threaded_oracle_equals_single_thread():
+    """The top level's buckets solved on several host threads give the same
+    bytes as one thread (sizes with one and two tiled levels, ragged)."""
+    for n, w in [(100_003, 4), ((1 << 21) + 77, 8), (300_001, 16)]:
+        h = workloads.random_values(n, w, 3)
+        p = oracle.default_params(n, w)
+        a = h.copy()
+        oracle.shuffle(a, 1234, p, stream_id=5)
+        b = h.copy()
+        oracle.shuffle(b, 1234, p, stream_id=5, threads=6)
+        assert np.array_equal(a, b), (n, w)
+
+
 def test_enumeration_detects_bias():
     """Sanity of the enumerator itself: Fisher-Yates with the partner drawn
     from [0, m) instead of [0, i] (a classic bias) is visibly non-uniform."""

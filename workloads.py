@@ -1,7 +1,7 @@
 """Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
 
 This module only builds inputs; it holds none of the shuffle's arithmetic.
-The paper evaluates on synthetic 64-bit integers (arXiv 2302.03317, Sec. 5);
+The paper evaluates on synthetic 64-bit integers (arXiv 2302.03317, Sec. 6);
 these generators produce arrays of the same kind at the sizes the benchmark
 and tests use.
 """
@@ -80,3 +80,14 @@ def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
     """Arrival times (seconds from 0) of a Poisson process of `rate` per second."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def identity_mod32(n: int) -> np.ndarray:
+    """uint32 array whose element i holds i mod 2^32 (an identity that wraps,
+    for uint32 arrays of more than 2^32 elements)."""
+    out = np.empty(n, dtype=np.uint32)
+    chunk = 1 << 28
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        out[a:b] = (np.arange(a, b, dtype=np.uint64) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    return out
