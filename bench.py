@@ -410,6 +410,19 @@ def main() -> int:
         "bytes_per_launch": per_launch_bytes,
         "avg_launch_ms": per_launch_s * 1e3,
     }
+    # the whole step: every kernel's algorithmic bytes (each element a kernel
+    # moves counted once read and once written) over the step time
+    step_bytes = sum(v["bytes"] for v in kt.values()) / args.steps
+    step_gbs = step_bytes / (ms_per_step / 1e3) / 1e9
+    step_roofline = {
+        "bound": "hbm",
+        "algorithmic_bytes_per_step": step_bytes,
+        "achieved": step_gbs,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": step_gbs / HBM_PEAK_GBS,
+        "target_frac": 0.6,
+    }
     line = {
         "metric": "Gelem/s and achieved HBM GB/s (% of peak), single vs batched, bit-exact",
         "value": gelem,
@@ -434,6 +447,7 @@ def main() -> int:
         "useful_GBs": useful_gbs,
         "useful_frac_of_peak": useful_gbs / HBM_PEAK_GBS,
         "roofline": roofline,
+        "step_roofline": step_roofline,
         "kernels": kernels,
         "levels": {"tiled_levels": stats["tiled_levels"], "movers_last_step": stats["movers"],
                    "leaves_last_step": stats["leaves"], "workspace_bytes": stats["workspace_bytes"]},
