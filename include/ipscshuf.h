@@ -146,6 +146,26 @@ int shuffle_inplace_ws(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed
                        uint32_t stream_id, const shuf_params_t* params, void* workspace,
                        uint64_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid device allocation): shuffle_inplace_ex
+ * with every device buffer -- level tables, the movers' workspace, leaf lists,
+ * counters -- taken from a static device array of the library (64 MiB per
+ * device, part of its code object, held until the process ends) and host
+ * staging from a static host array.  The call makes no hipMalloc, hipFree,
+ * hipHostMalloc or hipEventCreate (timing is off for it); its host-side
+ * bookkeeping uses the C++ heap.  It first runs the planning part of the
+ * shuffle in that memory, so a shortage is reported before any element moves.
+ * The output equals shuffle_inplace_ex with the same arguments.
+ *   ptr, n, elem_bytes, seed, stream_id, params, stream: as shuffle_inplace_ex
+ * Limits: n * elem_bytes <= 48 MiB, else SHUF_EUNSUPPORTED before any GPU
+ * work; SHUF_ENOMEM (data untouched) when the parameters need more than the
+ * static memory holds.  Calls on one device share its static array; the
+ * library serialises them, so calls that reach the device concurrently from
+ * outside the library (e.g. a second copy of the library) would race.
+ * Errors otherwise as shuffle_inplace_ex. */
+int shuffle_inplace_noalloc(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                            uint32_t stream_id, const shuf_params_t* params, void* stream);
+
 /* Shuffle `count` independent arrays packed back to back at ptr, each in
  * place: many independent shuffles run concurrently, the setting of
  * Sec. 6.3, here in shared launches instead of one task per array.  Array j occupies elements [offsets[j], offsets[j+1]) and is shuffled

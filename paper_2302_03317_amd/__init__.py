@@ -132,6 +132,8 @@ def lib() -> ctypes.CDLL:
         L.shuffle_timing_enable.restype = i
         L.shuffle_timing_read.argtypes = [ctypes.POINTER(_KernelTime)]
         L.shuffle_timing_read.restype = i
+        L.shuffle_inplace_noalloc.argtypes = [vp, u64, u32, u64, u32, ctypes.POINTER(_Params), vp]
+        L.shuffle_inplace_noalloc.restype = i
         L.shuffle_release.argtypes = []
         L.shuffle_release.restype = i
         _lib = L
@@ -245,6 +247,21 @@ def shuffle_inplace_ws(tensor, seed: int, workspace, stream_id: int = 0,
     )
     if rc != SHUF_OK:
         raise ShuffleError(rc, "shuffle_inplace_ws")
+
+
+def shuffle_inplace_noalloc(tensor, seed: int, stream_id: int = 0, params: Params | None = None,
+                            stream=None) -> None:
+    """shuffle_inplace_ex without any device allocation: every buffer comes
+    from the library's static device array (arrays up to 48 MiB)."""
+    n, w = _geometry(tensor)
+    p = params if params is not None else default_params(n, w)
+    cp = _Params(p.tile, p.kmax_log2, p.n0, p.lmax)
+    rc = lib().shuffle_inplace_noalloc(
+        ctypes.c_void_p(tensor.data_ptr()), n, w, seed & (2**64 - 1), stream_id, ctypes.byref(cp),
+        _stream_handle(tensor, stream),
+    )
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_inplace_noalloc")
 
 
 def shuffle_batched(tensor, offsets, seed: int, stream=None) -> None:

@@ -21,6 +21,13 @@
 #include "ipscshuf.h"
 #include "kernels.hpp"
 
+// Device memory of the allocation-free entry point (shuffle_inplace_noalloc):
+// one array per device, part of this file's code object, held until the
+// process ends.  Host code must not pass `scratch` itself to a kernel (on the
+// host the name is a stand-in, not a device address): it takes the device
+// address once per device with hipGetSymbolAddress and uses only that.
+__device__ __align__(256) uint8_t scratch[64ull << 20];
+
 namespace ipss {
 namespace {
 
@@ -30,15 +37,19 @@ constexpr uint64_t kMaxElements = 1ull << 40;
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    bool fixed = false;  // a region of memory the buffer does not own: never freed or grown
     void release()
     {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
+        if (p && !fixed) (void)hipFree(p);
+        if (!fixed) {
+            p = nullptr;
+            cap = 0;
+        }
     }
     hipError_t ensure(size_t bytes)
     {
         if (bytes <= cap && p) return hipSuccess;
+        if (fixed) return hipErrorOutOfMemory;
         if (p) {
             hipError_t e = hipDeviceSynchronize();
             if (e != hipSuccess) return e;
@@ -65,6 +76,7 @@ struct DevBuf {
 hipError_t grow_keep(DevBuf& d, size_t bytes, size_t used, hipStream_t s)
 {
     if (bytes <= d.cap && d.p) return hipSuccess;
+    if (d.fixed) return hipErrorOutOfMemory;
     void* np = nullptr;
     const size_t want = std::max<size_t>(bytes + bytes / 2, 4096);
     hipError_t e = hipMalloc(&np, want);
@@ -118,15 +130,19 @@ struct Mem {
 struct HostBuf {
     void* p = nullptr;
     size_t cap = 0;
+    bool fixed = false;  // a region of (pageable) host memory the buffer does not own
     void release()
     {
-        if (p) (void)hipHostFree(p);
-        p = nullptr;
-        cap = 0;
+        if (p && !fixed) (void)hipHostFree(p);
+        if (!fixed) {
+            p = nullptr;
+            cap = 0;
+        }
     }
     hipError_t ensure(size_t bytes)
     {
         if (bytes <= cap && p) return hipSuccess;
+        if (fixed) return hipErrorOutOfMemory;
         if (p) {
             (void)hipHostFree(p);
             p = nullptr;
@@ -157,14 +173,43 @@ struct LeafLists {
     }
 };
 
+// Host staging of one engine step: uploads of the level's subproblems and
+// fallback items, read-backs of the level totals, counters, error flag and
+// the subproblems of the next level.
+struct HostSet {
+    HostBuf subs, total, big, gfy, err, counters;
+    void release()
+    {
+        for (HostBuf* h : {&subs, &total, &big, &gfy, &err, &counters}) h->release();
+    }
+};
+
+// The allocation-free entry point's memory on one device: the static scratch
+// array (its device address, taken once per device) split into the probe's
+// word, two leaf lists and the per-step arena; host staging in a static
+// pageable array.
+constexpr uint64_t kScratchBytes = 64ull << 20;
+constexpr uint64_t kScratchListBytes = 4ull << 20;  // each of the two leaf lists
+constexpr uint64_t kScratchProbeBytes = 256;
+constexpr uint64_t kNoAllocHostBytes = 256ull << 10;
+constexpr uint64_t kNoAllocMaxDataBytes = 48ull << 20;  // larger arrays are rejected up front
+
+struct NoAllocState {
+    bool ready = false;
+    uint8_t* scratch = nullptr;  // device address of `scratch` on this device
+    LeafLists lists;
+    HostSet host;
+};
+
 struct Context {
     std::mutex mu;
     LeafLists lists;  // used by blocking calls (under mu)
     bool init = false;
     bool rank_atomic = false;  // see Params::rank_atomic
     DevBuf subs, tile_sub, tile_pofs, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, wsp, total, ws,
-        leaves, leaves_cls, big, gfy, err, counters;
-    HostBuf h_subs, h_total, h_leaves, h_big, h_gfy, h_err, h_counters;
+        leaves, leaves_cls, big, gfy, err, counters, probe;
+    HostSet host;
+    NoAllocState na;
     std::vector<SubDesc> hv_subs;  // the level's subproblems (kept to reuse its memory)
     shuf_stats_t stats{};
     // timing
@@ -251,10 +296,9 @@ void release_all()
         (void)hipDeviceSynchronize();
         for (DevBuf* b : {&C.subs, &C.tile_sub, &C.tile_pofs, &C.chunk_sub, &C.bk_sub, &C.cnt, &C.mpre,
                           &C.kpre, &C.chA, &C.chB, &C.N, &C.S, &C.M, &C.K, &C.MB, &C.wsp, &C.total,
-                          &C.ws, &C.leaves, &C.leaves_cls, &C.big, &C.gfy, &C.err, &C.counters})
+                          &C.ws, &C.leaves, &C.leaves_cls, &C.big, &C.gfy, &C.err, &C.counters, &C.probe})
             b->release();
-        for (HostBuf* h : {&C.h_subs, &C.h_total, &C.h_leaves, &C.h_big, &C.h_gfy, &C.h_err, &C.h_counters})
-            h->release();
+        C.host.release();
         C.lists.release();
         for (hipEvent_t e : C.event_pool) (void)hipEventDestroy(e);
         C.event_pool.clear();
@@ -265,6 +309,47 @@ void release_all()
 }
 
 std::once_flag g_exit_hook;
+
+// Host staging of the allocation-free entry point, one static area per
+// device (pageable: nothing is registered or pinned).
+alignas(256) uint8_t g_noalloc_host[kMaxDevices][kNoAllocHostBytes];
+
+// Set-up of the allocation-free entry point on the current device (under the
+// context's lock): the device address of `scratch` on this device, and the
+// fixed regions carved from it and from the static host area.
+int noalloc_setup(Context& C, int dev)
+{
+    NoAllocState& na = C.na;
+    if (na.ready) return SHUF_OK;
+    static_assert(sizeof(scratch) == kScratchBytes, "scratch size");
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return SHUF_EHIP;
+    na.scratch = static_cast<uint8_t*>(ptr);
+    for (int i = 0; i < 2; ++i) {
+        na.lists.leaves[i].p = na.scratch + kScratchProbeBytes + i * kScratchListBytes;
+        na.lists.leaves[i].cap = kScratchListBytes;
+        na.lists.leaves[i].fixed = true;
+    }
+    // host area: new-leaf staging, subproblem uploads, fallback uploads,
+    // next-level subproblems, and the small read-backs
+    uint8_t* h = g_noalloc_host[dev];
+    const uint64_t part = kNoAllocHostBytes / 4;
+    HostBuf* bufs[4] = {&na.lists.h_new, &na.host.subs, &na.host.gfy, &na.host.big};
+    for (int i = 0; i < 4; ++i) {
+        bufs[i]->p = h + i * part;
+        bufs[i]->cap = part - 256;
+        bufs[i]->fixed = true;
+    }
+    HostBuf* small[3] = {&na.host.total, &na.host.err, &na.host.counters};
+    for (int i = 0; i < 3; ++i) {
+        small[i]->p = h + 3 * part + (part - 256) + 64 * i;
+        small[i]->cap = 64;
+        small[i]->fixed = true;
+    }
+    na.ready = true;
+    return SHUF_OK;
+}
 
 struct HostSub {
     uint64_t elem_off, base, m, seed;
@@ -349,6 +434,9 @@ struct Engine {
     uint64_t next_ticket = 1, inflight = 0;
     bool broken = false;
     bool dry = false;  // planning run: counts and tables only, no element moves
+    bool noalloc = false;  // every buffer from the static scratch: no allocation, no timing events
+    HostSet* host = nullptr;  // host staging (the context's, or the static one)
+    void* probe_buf = nullptr;  // device word for the lane-order probe (allocation-free runs)
     Mem mem;
 };
 
@@ -397,7 +485,14 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
         // stable ranks by LDS atomics where the device serves them in lane
         // order; IPSCSHUF_RANK=ballot keeps the ballot method
         bool lane_ordered = false;
-        HIP_TRY(probe_lds_lane_order(stream, &lane_ordered));
+        void* pbuf = nullptr;
+        if (E.noalloc) {
+            pbuf = E.probe_buf;  // the first word of the static scratch
+        } else {
+            HIP_TRY(C.probe.ensure(kScratchProbeBytes));
+            pbuf = C.probe.p;
+        }
+        HIP_TRY(probe_lds_lane_order(stream, static_cast<unsigned long long*>(pbuf), &lane_ordered));
         const char* rank_env = std::getenv("IPSCSHUF_RANK");
         C.rank_atomic = lane_ordered && !(rank_env && std::strcmp(rank_env, "ballot") == 0);
         C.init = true;
@@ -407,19 +502,20 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     const uint32_t kmax = 1u << prm.kmax_log2;
     const uint64_t tile_limit = prm.tile - kmax;  // subproblems up to this size finish in LDS
     const bool dry = E.dry;
-    TimingOff timing_guard(C, dry);
+    TimingOff timing_guard(C, dry || E.noalloc);
+    HostSet& H = *E.host;
     Mem& mem = E.mem;
     mem.begin_step();
     void *p_err, *p_counters, *p_total;
     HIP_TRY(mem.take(C.err, 4, &p_err));
-    HIP_TRY(C.h_err.ensure(4));
+    HIP_TRY(H.err.ensure(4));
     HIP_TRY(hipMemsetAsync(p_err, 0, 4, stream));
     HIP_TRY(mem.take(C.counters, 48, &p_counters));
-    HIP_TRY(C.h_counters.ensure(48));
+    HIP_TRY(H.counters.ensure(48));
     HIP_TRY(mem.take(C.total, 8, &p_total));
-    HIP_TRY(C.h_total.ensure(8));
+    HIP_TRY(H.total.ensure(8));
     unsigned long long* dc = static_cast<unsigned long long*>(p_counters);
-    unsigned long long* hc = C.h_counters.as<unsigned long long>();
+    unsigned long long* hc = H.counters.as<unsigned long long>();
     // [0] leaf children, [1] big children, [2] leaf child elements, [3..5] leaves per class
     HIP_TRY(hipMemsetAsync(dc, 0, 48, stream));
 
@@ -505,7 +601,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
         for (const SubDesc& d : subs) level_elems += d.m;
         void *p_subs, *p_tile_sub, *p_tile_pofs, *p_chunk_sub, *p_bk_sub, *p_cnt, *p_mpre, *p_kpre, *p_chA, *p_chB,
             *p_N, *p_S, *p_M, *p_K, *p_MB, *p_wsp;
-        HIP_TRY(upload(mem, C.subs, C.h_subs, subs, stream, &p_subs));
+        HIP_TRY(upload(mem, C.subs, H.subs, subs, stream, &p_subs));
         // tile / chunk / bucket -> subproblem maps, built on the device
         HIP_TRY(mem.take(C.tile_sub, ntiles * 4, &p_tile_sub));
         HIP_TRY(mem.take(C.tile_pofs, ntiles * 16, &p_tile_pofs));
@@ -566,7 +662,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
                                     static_cast<LeafDesc*>(E.lists->leaves[1 - E.which].p),
                                     static_cast<LeafDesc*>(p_big), dc, stream));
         }
-        HIP_TRY(hipMemcpyAsync(C.h_total.p, T.total, 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(H.total.p, T.total, 8, hipMemcpyDeviceToHost, stream));
     }
     HIP_TRY(hipMemcpyAsync(hc, dc, 48, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -578,13 +674,13 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     }
 
     if (!tiled.empty()) {
-        const uint64_t movers = C.h_total.as<uint64_t>()[0];
+        const uint64_t movers = H.total.as<uint64_t>()[0];
         if (nbig) {
-            HIP_TRY(C.h_big.ensure(nbig * sizeof(LeafDesc)));
-            HIP_TRY(hipMemcpyAsync(C.h_big.p, p_big, nbig * sizeof(LeafDesc),
+            HIP_TRY(H.big.ensure(nbig * sizeof(LeafDesc)));
+            HIP_TRY(hipMemcpyAsync(H.big.p, p_big, nbig * sizeof(LeafDesc),
                                    hipMemcpyDeviceToHost, stream));
             HIP_TRY(hipStreamSynchronize(stream));
-            const LeafDesc* bl = C.h_big.as<LeafDesc>();
+            const LeafDesc* bl = H.big.as<LeafDesc>();
             for (uint64_t i = 0; i < nbig; ++i)
                 E.cur.push_back({bl[i].elem_off, bl[i].base, bl[i].m, bl[i].seed, bl[i].level,
                                  bl[i].stream_id, bl[i].owner});
@@ -616,7 +712,7 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     }
     if (!gfy.empty()) {
         void* p_gfy;
-        HIP_TRY(upload(mem, C.gfy, C.h_gfy, gfy, stream, &p_gfy));
+        HIP_TRY(upload(mem, C.gfy, H.gfy, gfy, stream, &p_gfy));
         uint64_t elems = 0;
         for (const LeafDesc& l : gfy) elems += l.m;
         if (!dry) {
@@ -624,9 +720,9 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
             HIP_TRY(launch_fy_global(w, static_cast<const LeafDesc*>(p_gfy), gfy.size(), stream));
         }
     }
-    HIP_TRY(hipMemcpyAsync(C.h_err.p, p_err, 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(H.err.p, p_err, 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    if (C.h_err.as<uint32_t>()[0] != 0) {  // an index check failed in a kernel
+    if (H.err.as<uint32_t>()[0] != 0) {  // an index check failed in a kernel
         E.broken = true;
         return SHUF_EHIP;
     }
@@ -657,22 +753,29 @@ Context* current_context(int* dev_out = nullptr)
     return &g_ctx[dev];
 }
 
+// Run an engine's submitted work to completion, under the context's lock.
+int engine_run_locked(Context& C, Engine& E, void* stream)
+{
+    C.spans.clear();
+    C.events_used = 0;
+    if (!E.lists) E.lists = &C.lists;
+    if (!E.host) E.host = &C.host;
+    shuf_stats_t st{};
+    while (E.inflight) {
+        const int rc = engine_step(C, E, static_cast<hipStream_t>(stream), st);
+        if (rc != SHUF_OK) return rc;
+    }
+    if (!E.dry) C.stats = st;
+    return SHUF_OK;
+}
+
 // Run an engine's submitted work to completion (blocking calls).
 int engine_drain(Engine& E, void* stream)
 {
     Context* C = current_context();
     if (!C) return SHUF_EHIP;
     std::lock_guard<std::mutex> lock(C->mu);
-    C->spans.clear();
-    C->events_used = 0;
-    E.lists = &C->lists;
-    shuf_stats_t st{};
-    while (E.inflight) {
-        const int rc = engine_step(*C, E, static_cast<hipStream_t>(stream), st);
-        if (rc != SHUF_OK) return rc;
-    }
-    if (!E.dry) C->stats = st;
-    return SHUF_OK;
+    return engine_run_locked(*C, E, stream);
 }
 
 Engine make_engine(uint32_t w, const shuf_params_t& p)
@@ -764,6 +867,44 @@ int shuffle_inplace_ws(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed
     E.mem.size = workspace_bytes;
     engine_submit(E, reinterpret_cast<uintptr_t>(ptr) / elem_bytes, n, seed, stream_id);
     return engine_drain(E, stream);
+}
+
+int shuffle_inplace_noalloc(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                            uint32_t stream_id, const shuf_params_t* params, void* stream)
+{
+    if (!valid_width(elem_bytes)) return SHUF_EINVAL;
+    int rc = check_params(params, elem_bytes);
+    if (rc != SHUF_OK) return rc;
+    if (n <= 1) return SHUF_OK;
+    if (!ptr) return SHUF_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ptr) % elem_bytes) return SHUF_EINVAL;
+    if (n >= kMaxElements || n * elem_bytes > kNoAllocMaxDataBytes) return SHUF_EUNSUPPORTED;
+    int dev = 0;
+    Context* C = current_context(&dev);
+    if (!C) return SHUF_EHIP;
+    std::lock_guard<std::mutex> lock(C->mu);
+    rc = noalloc_setup(*C, dev);
+    if (rc != SHUF_OK) return rc;
+    NoAllocState& na = C->na;
+    const uint64_t lead = kScratchProbeBytes + 2 * kScratchListBytes;
+    // A planning run in the scratch first: every buffer of every step is
+    // taken exactly as in the shuffle itself, so a shortage is reported
+    // before any element moves.
+    for (int pass = 0; pass < 2; ++pass) {
+        Engine E = make_engine(elem_bytes, *params);
+        E.noalloc = true;
+        E.dry = pass == 0;
+        E.mem.mode = Mem::kArena;
+        E.mem.base = na.scratch + lead;
+        E.mem.size = kScratchBytes - lead;
+        E.lists = &na.lists;
+        E.host = &na.host;
+        E.probe_buf = na.scratch;
+        engine_submit(E, reinterpret_cast<uintptr_t>(ptr) / elem_bytes, n, seed, stream_id);
+        rc = engine_run_locked(*C, E, stream);
+        if (rc != SHUF_OK) return rc;
+    }
+    return SHUF_OK;
 }
 
 int shuffle_inplace(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, void* stream)
@@ -874,6 +1015,7 @@ int shuf_session_step(shuf_session_t* s, void* stream, uint64_t* done, uint64_t 
         std::lock_guard<std::mutex> lock(C->mu);
         C->spans.clear();
         C->events_used = 0;
+        s->E.host = &C->host;
         shuf_stats_t st{};
         const int rc = engine_step(*C, s->E, static_cast<hipStream_t>(stream), st);
         if (rc != SHUF_OK) {

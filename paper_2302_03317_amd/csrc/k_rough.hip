@@ -456,21 +456,17 @@ hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_su
     }
 }
 
-hipError_t probe_lds_lane_order(hipStream_t stream, bool* lane_ordered)
+hipError_t probe_lds_lane_order(hipStream_t stream, unsigned long long* d, bool* lane_ordered)
 {
     *lane_ordered = false;
-    unsigned long long* d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(unsigned long long));
-    if (e != hipSuccess) return e;
     unsigned long long h = 1;
-    e = hipMemsetAsync(d, 0, sizeof(unsigned long long), stream);
+    hipError_t e = hipMemsetAsync(d, 0, sizeof(unsigned long long), stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_lane_order_probe, dim3(1024), dim3(256), 0, stream, 64u, d);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    (void)hipFree(d);
     if (e != hipSuccess) return e;
     *lane_ordered = h == 0;
     return hipSuccess;

@@ -21,8 +21,9 @@ hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_su
                         const Params& prm, hipStream_t stream);
 hipError_t set_rough_lds_limits();
 // Whether one wave's same-address LDS atomic adds return in lane order on the
-// current device (a probe kernel over random label patterns, run once).
-hipError_t probe_lds_lane_order(hipStream_t stream, bool* lane_ordered);
+// current device (a probe kernel over random label patterns, run once);
+// `d` is one device word of the caller's.
+hipError_t probe_lds_lane_order(hipStream_t stream, unsigned long long* d, bool* lane_ordered);
 // The count table of one tiled level without moving elements (planning).
 hipError_t launch_count(const SubDesc* subs, const uint32_t* tile_sub, const uint64_t* tile_pofs,
                         uint32_t* cnt_tab, uint64_t ntiles, hipStream_t stream);
