@@ -116,7 +116,8 @@ PAPER_CONTEXT = {
 }
 
 
-def host_description() -> str:
+def host_description() -> dict:
+    """CPU model, the logical CPUs this process may use, and the RAM."""
     model = "unknown CPU"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -126,49 +127,96 @@ def host_description() -> str:
                     break
     except OSError:
         pass
-    return f"{model}, {os.cpu_count()} logical CPUs visible"
+    ram = None
+    try:
+        with open("/proc/meminfo") as fh:
+            for ln in fh:
+                if ln.startswith("MemTotal:"):
+                    ram = int(ln.split()[1]) * 1024
+                    break
+    except OSError:
+        pass
+    cpus = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu": model, "logical_cpus_usable": cpus, "logical_cpus_total": os.cpu_count(),
+            "ram_bytes": ram}
 
 
-def cpu_baseline(log2n: int, w: int) -> dict:
-    """The CPU oracle (single thread) on a bounded sample of the workload."""
+def host_threads() -> int:
+    """Threads for the multi-core CPU baselines: the CPUs this process may
+    use, at most OMP_NUM_THREADS when it is set."""
+    cpus = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        cpus = min(cpus, int(env))
+    return max(1, cpus)
+
+
+def protocol_time(work, make_buffer, n: int, runs: int = 5, min_run_s: float = 0.1) -> dict:
+    """The paper's timing protocol (Sec. 6): the mean of `runs` runs, each
+    averaging repetitions that total at least min_run_s, on cold data: every
+    run works on its own buffer, and the buffers together exceed 512 MB (or
+    the run's data is larger than that itself)."""
     import numpy as np
 
+    first = make_buffer()
+    nbuf = max(2, min(16, -(-(512 << 20) // max(1, first.nbytes)) + 1))
+    bufs = [first] + [make_buffer() for _ in range(nbuf - 1)]
+    per_run = []
+    for r in range(runs):
+        a = bufs[r % nbuf]
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            work(a, 0x5EED + 1000 * r + reps)
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_run_s:
+                break
+        per_run.append(dt / reps)
+    mean = float(np.mean(per_run))
+    return {"value": n / mean / 1e9, "unit": "Gelem/s", "seconds_per_shuffle": mean,
+            "runs": runs, "run_seconds": [round(x, 4) for x in per_run],
+            "buffer_bytes": int(bufs[0].nbytes), "buffers": nbuf}
+
+
+def cpu_baselines(log2n: int, w: int, pip_log2n: int) -> dict:
+    """CPU baselines on the host, each by the paper's protocol: the oracle on
+    one core and on all usable cores (its buckets after the first level on
+    host threads), textbook Fisher-Yates with the oracle's draws on one core,
+    the paper's own parallel algorithm (host PIpScShuf) on all usable cores,
+    and sequential Fisher-Yates with its generator on one core."""
+    import hostshuf
     import oracle
     import workloads
 
     n = 1 << log2n
-    a = workloads.identity(n, w)
-    t0 = time.perf_counter()
-    oracle.shuffle(a, 0x5EED, oracle.default_params(n, w))
-    dt = time.perf_counter() - t0
-    return {
-        "value": n / dt / 1e9,
-        "unit": "Gelem/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"one shuffle of 2^{log2n} {w}-byte identity elements, default parameters, "
-                  f"{dt:.1f} s on one host core",
-        "host": host_description(),
-    }
-
-
-def cpu_fisher_yates(log2n: int, w: int) -> dict:
-    """Textbook sequential Fisher-Yates (the oracle's draws) on one host core."""
-    import oracle
-    import workloads
-
-    n = 1 << log2n
-    a = workloads.identity(n, w)
-    t0 = time.perf_counter()
-    oracle.fisher_yates(a, 0x5EED)
-    dt = time.perf_counter() - t0
-    return {
-        "value": n / dt / 1e9,
-        "unit": "Gelem/s",
-        "cores": 1,
-        "kind": "sequential Fisher-Yates",
-        "sample": f"2^{log2n} {w}-byte identity elements, {dt:.1f} s on one host core",
-    }
+    params = oracle.default_params(n, w)
+    threads = host_threads()
+    host = host_description()
+    # cold data: enough buffers that they exceed 512 MB together
+    mk = lambda: workloads.identity(n, w)  # noqa: E731
+    out = {}
+    t = protocol_time(lambda a, s: oracle.shuffle(a, s, params), mk, n)
+    out["cpu_baseline"] = dict(t, cores=1, kind="oracle",
+                               sample=f"shuffles of 2^{log2n} {w}-byte elements (a bounded sample of the "
+                                      f"workload), default parameters, one host thread, mean of 5 runs of "
+                                      f">= 0.1 s on cold buffers", host=host)
+    t = protocol_time(lambda a, s: oracle.shuffle(a, s, params, threads=threads), mk, n)
+    out["cpu_oracle_threads"] = dict(t, cores=threads, kind="oracle, top-level buckets on host threads",
+                                     sample=f"2^{log2n} {w}-byte elements")
+    t = protocol_time(lambda a, s: oracle.fisher_yates(a, s), mk, n)
+    out["cpu_fisher_yates"] = dict(t, cores=1, kind="sequential Fisher-Yates, the oracle's Philox draws",
+                                   sample=f"2^{log2n} {w}-byte elements")
+    npip = 1 << pip_log2n
+    t = protocol_time(lambda a, s: hostshuf.shuffle(a, s, threads=threads),
+                      lambda: workloads.identity(npip, w), npip)
+    out["cpu_pipscshuf"] = dict(t, cores=threads,
+                                kind="host PIpScShuf (the paper's parallel algorithm, Sec. 3-5; its own "
+                                     "generator, so not the GPU's permutation)",
+                                sample=f"2^{pip_log2n} {w}-byte elements")
+    t = protocol_time(lambda a, s: hostshuf.fisher_yates(a, s), mk, n)
+    out["cpu_fisher_yates_pcg"] = dict(t, cores=1, kind="sequential Fisher-Yates, 128-bit MCG generator",
+                                       sample=f"2^{log2n} {w}-byte elements")
+    return out
 
 
 def batched_compare(torch, shuf, count: int = 10000, seed: int = 2026) -> dict:
@@ -314,7 +362,8 @@ def main() -> int:
                          "copy of known size for scaling HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rates", default="1000,2000,4000,8000,16000")
-    ap.add_argument("--cpu-sample-log2", type=int, default=26)
+    ap.add_argument("--cpu-sample-log2", type=int, default=24)
+    ap.add_argument("--cpu-pip-log2", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -458,8 +507,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         line["batched"] = batched_compare(torch, shuf)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(min(args.cpu_sample_log2, log2n), w)
-        line["cpu_fisher_yates"] = cpu_fisher_yates(min(args.cpu_sample_log2, log2n), w)
+        line.update(cpu_baselines(min(args.cpu_sample_log2, log2n), w, min(args.cpu_pip_log2, log2n)))
     line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
     return 0 if before == after else 1
