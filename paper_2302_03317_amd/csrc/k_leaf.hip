@@ -75,28 +75,34 @@ __device__ __forceinline__ void fy_segment(uint16_t* idx, uint32_t s0, uint32_t 
 }
 
 // Whole-workgroup stable split of segment [s0, s0 + len) by KAPPA-bit labels;
-// children (start, length) go to out[0..k).
+// children (start, length) go to out[0..k).  On a leaf's first split
+// (`first`) the segment is the whole leaf in its initial order, so the item
+// at position x is leaf item x and the index array is not read (nor need it
+// have been written).  Labels stay in registers between the ranking and the
+// placement; the bucket offsets are folded into the per-wave offsets so that
+// the placement reads one counter per item.
 template <int KAPPA, int ROUNDS, bool ATOMIC>
 __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* lab, uint32_t* H,
                                                 uint32_t hs, uint32_t* out, uint32_t s0,
                                                 uint32_t len, uint32_t tid, uint32_t wv,
-                                                uint32_t lane)
+                                                uint32_t lane, bool first)
 {
     constexpr uint32_t k = 1u << KAPPA, sh = 8 - KAPPA;
     uint32_t* Htot = H + kWaves * hs;
     const uint32_t end = s0 + len;
     const uint32_t per_wave = ((len + kWaves * 64 - 1) / (kWaves * 64)) * 64;
     const uint32_t rounds = per_wave / 64;
-    const uint32_t first = s0 + wv * per_wave + lane;
+    const uint32_t first_x = s0 + wv * per_wave + lane;
     for (uint32_t j = tid; j < (kWaves + 1) * hs; j += kThreads) H[j] = 0;
     __syncthreads();
     uint32_t pk[ROUNDS];
+    uint32_t lb[(ROUNDS + 3) / 4];
 #pragma unroll
     for (uint32_t r = 0; r < static_cast<uint32_t>(ROUNDS); ++r) {
-        const uint32_t x = first + 64u * r;
-        uint32_t v = 0;
+        const uint32_t x = first_x + 64u * r;
+        uint32_t v = 0, l = 0;
         if (r < rounds && x < end) {
-            const uint32_t l = lab[x] >> sh;
+            l = lab[x] >> sh;
             uint32_t rank;
             if (ATOMIC) {
                 rank = atomicAdd(&H[wv * hs + l], 1u);  // lane-ordered: the stable rank
@@ -107,9 +113,11 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
                 if (below == 0) H[wv * hs + l] = old + static_cast<uint32_t>(__popcll(peers));
                 rank = old + below;
             }
-            v = static_cast<uint32_t>(idx[x]) | (rank << 16);
+            v = (first ? x : static_cast<uint32_t>(idx[x])) | (rank << 16);
         }
         pk[r] = v;
+        if (r % 4 == 0) lb[r / 4] = l;
+        else lb[r / 4] |= l << (8 * (r % 4));
     }
     __syncthreads();
     for (uint32_t l = tid; l < k; l += kThreads) {
@@ -124,36 +132,42 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
     __syncthreads();
     if (wv == 0) wave_exclusive_scan(Htot, k);
     __syncthreads();
-    for (uint32_t l = tid; l < k; l += kThreads)
-        out[l] = seg_pack(s0 + Htot[l], Htot[l + 1] - Htot[l]);
+    for (uint32_t l = tid; l < k; l += kThreads) {
+        const uint32_t base = s0 + Htot[l];
+        out[l] = seg_pack(base, Htot[l + 1] - Htot[l]);
+        for (int w = 0; w < kWaves; ++w) H[w * hs + l] += base;
+    }
+    __syncthreads();
 #pragma unroll
     for (uint32_t r = 0; r < static_cast<uint32_t>(ROUNDS); ++r) {
-        const uint32_t x = first + 64u * r;
+        const uint32_t x = first_x + 64u * r;
         if (r < rounds && x < end) {
-            const uint32_t l = lab[x] >> sh;
-            idx[s0 + Htot[l] + H[wv * hs + l] + (pk[r] >> 16)] = static_cast<uint16_t>(pk[r]);
+            const uint32_t l = (lb[r / 4] >> (8 * (r % 4))) & 0xFFu;
+            idx[H[wv * hs + l] + (pk[r] >> 16)] = static_cast<uint16_t>(pk[r]);
         }
     }
     __syncthreads();
 }
 
-// One wave's stable split of segment [s0, s0 + len), len <= 64 * ROUNDS.
+// One wave's stable split of segment [s0, s0 + len), len <= 64 * ROUNDS
+// (`first` as for split_workgroup).
 template <int KAPPA, int ROUNDS, bool ATOMIC>
 __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, uint32_t* Hw,
                                            uint32_t* out, uint32_t s0, uint32_t len,
-                                           uint32_t lane)
+                                           uint32_t lane, bool first)
 {
     constexpr uint32_t k = 1u << KAPPA, sh = 8 - KAPPA;
     const uint32_t end = s0 + len;
     for (uint32_t j = lane; j <= k; j += 64) Hw[j] = 0;
     const uint32_t rounds = (len + 63) / 64;
     uint32_t pk[ROUNDS];
+    uint32_t lb[(ROUNDS + 3) / 4];
 #pragma unroll
     for (uint32_t r = 0; r < static_cast<uint32_t>(ROUNDS); ++r) {
         const uint32_t x = s0 + 64u * r + lane;
-        uint32_t v = 0;
+        uint32_t v = 0, l = 0;
         if (r < rounds && x < end) {
-            const uint32_t l = lab[x] >> sh;
+            l = lab[x] >> sh;
             uint32_t rank;
             if (ATOMIC) {
                 rank = atomicAdd(&Hw[l], 1u);  // lane-ordered: the stable rank
@@ -164,9 +178,11 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
                 if (below == 0) Hw[l] = old + static_cast<uint32_t>(__popcll(peers));
                 rank = old + below;
             }
-            v = static_cast<uint32_t>(idx[x]) | (rank << 16);
+            v = (first ? x : static_cast<uint32_t>(idx[x])) | (rank << 16);
         }
         pk[r] = v;
+        if (r % 4 == 0) lb[r / 4] = l;
+        else lb[r / 4] |= l << (8 * (r % 4));
     }
     wave_exclusive_scan(Hw, k);
     for (uint32_t l = lane; l < k; l += 64) out[l] = seg_pack(s0 + Hw[l], Hw[l + 1] - Hw[l]);
@@ -174,7 +190,7 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
     for (uint32_t r = 0; r < static_cast<uint32_t>(ROUNDS); ++r) {
         const uint32_t x = s0 + 64u * r + lane;
         if (r < rounds && x < end) {
-            const uint32_t l = lab[x] >> sh;
+            const uint32_t l = (lb[r / 4] >> (8 * (r % 4))) & 0xFFu;
             idx[s0 + Hw[l] + (pk[r] >> 16)] = static_cast<uint16_t>(pk[r]);
         }
     }
@@ -214,10 +230,13 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
     // labraw holds whole label blocks; lab[x] is the label byte of position pbase + x
     const uint8_t* lab = labraw + (pbase & 15);
 
-    for (uint32_t x = tid; x < m; x += kThreads) idx[x] = static_cast<uint16_t>(x);
-
     // The first level has the single segment [0, m), classified right here.
+    // When it splits, the split writes the whole index array (the item at x
+    // is leaf item x until then); otherwise the identity is written here.
     uint32_t level = ld.level;
+    const bool first_split = m >= 2 && !(m <= prm.n0 || level >= prm.lmax);
+    if (!first_split)
+        for (uint32_t x = tid; x < m; x += kThreads) idx[x] = static_cast<uint16_t>(x);
     if (tid == 0) {
         const bool base = m <= prm.n0 || level >= prm.lmax;
         const bool split = m >= 2 && !base;
@@ -236,6 +255,7 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
         __syncthreads();
         const uint32_t nseg = misc[0];
         if (nseg == 0) break;
+        const bool first = level == ld.level;  // the single segment [0, m) in its initial order
         if (!classified) {
             // Base-case segments are listed longest first (counting sort on
             // the length, kept in the next-level list, which only the splits
@@ -302,25 +322,25 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
             uint32_t* out = nxt + tmpk[i];
             if (prm.rank_atomic) {
                 switch (kappa_in_tile(len, prm)) {
-                case 1: split_workgroup<1, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 2: split_workgroup<2, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 3: split_workgroup<3, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 4: split_workgroup<4, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 5: split_workgroup<5, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 6: split_workgroup<6, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 7: split_workgroup<7, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                default: split_workgroup<8, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 1: split_workgroup<1, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 2: split_workgroup<2, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 3: split_workgroup<3, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 4: split_workgroup<4, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 5: split_workgroup<5, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 6: split_workgroup<6, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 7: split_workgroup<7, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                default: split_workgroup<8, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
                 }
             } else {
                 switch (kappa_in_tile(len, prm)) {
-                case 1: split_workgroup<1, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 2: split_workgroup<2, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 3: split_workgroup<3, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 4: split_workgroup<4, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 5: split_workgroup<5, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 6: split_workgroup<6, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                case 7: split_workgroup<7, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
-                default: split_workgroup<8, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane); break;
+                case 1: split_workgroup<1, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 2: split_workgroup<2, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 3: split_workgroup<3, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 4: split_workgroup<4, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 5: split_workgroup<5, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 6: split_workgroup<6, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                case 7: split_workgroup<7, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
+                default: split_workgroup<8, ROUNDS, false>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
                 }
             }
         }
@@ -334,25 +354,25 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
             uint32_t* out = nxt + tmpk[i];
             if (prm.rank_atomic) {
                 switch (kappa_in_tile(len, prm)) {
-                case 1: split_wave<1, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
-                case 2: split_wave<2, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
-                case 3: split_wave<3, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
-                case 4: split_wave<4, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
-                case 5: split_wave<5, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
-                case 6: split_wave<6, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
-                case 7: split_wave<7, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
-                default: split_wave<8, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane); break;
+                case 1: split_wave<1, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 2: split_wave<2, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 3: split_wave<3, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 4: split_wave<4, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 5: split_wave<5, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 6: split_wave<6, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 7: split_wave<7, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane, first); break;
+                default: split_wave<8, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane, first); break;
                 }
             } else {
                 switch (kappa_in_tile(len, prm)) {
-                case 1: split_wave<1, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
-                case 2: split_wave<2, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
-                case 3: split_wave<3, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
-                case 4: split_wave<4, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
-                case 5: split_wave<5, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
-                case 6: split_wave<6, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
-                case 7: split_wave<7, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
-                default: split_wave<8, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane); break;
+                case 1: split_wave<1, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 2: split_wave<2, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 3: split_wave<3, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 4: split_wave<4, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 5: split_wave<5, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 6: split_wave<6, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane, first); break;
+                case 7: split_wave<7, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane, first); break;
+                default: split_wave<8, ROUNDS, false>(idx, lab, Hw, out, s0, len, lane, first); break;
                 }
             }
         }
