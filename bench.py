@@ -253,6 +253,42 @@ def batched_compare(torch, shuf, count: int = 10000, seed: int = 2026) -> dict:
     torch.cuda.synchronize()
     t_single = (time.perf_counter() - t0) / reps
     same = bool(torch.equal(a, b))
+    # algorithmic bytes of one blocking batched call (every element each kernel
+    # moves counted once read and once written), from the library's spans
+    shuf.timing_enable(True)
+    shuf.shuffle_batched(a, offs, seed_t + 99)
+    torch.cuda.synchronize()
+    call_bytes = sum(v["bytes"] for v in shuf.timing_read().values())
+    shuf.timing_enable(False)
+    # the enqueue-only form: eager calls, and one call captured into a graph
+    # and replayed (each replay shuffles the batch again with the captured seed)
+    wsb = shuf.batched_async_workspace_bytes(count, total, 4)
+    ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda:0")
+    o = torch.tensor(np.asarray(offs, dtype=np.int64), device="cuda:0")
+    shuf.shuffle_batched_async(a, o, s0, ws, total)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        shuf.shuffle_batched_async(a, o, seed_t + r, ws, total)
+    torch.cuda.synchronize()
+    t_async = (time.perf_counter() - t0) / reps
+    async_err = int(ws[:4].view(torch.int32).item())
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(gs):
+        with torch.cuda.graph(graph, stream=gs):
+            shuf.shuffle_batched_async(a, o, seed_t + 1234, ws, total, stream=gs)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    graph_err = int(ws[:4].view(torch.int32).item())
+    del graph, ws
     return {
         "workload": f"{count} u32 arrays, sizes floor(2^(4+16U)), {total} elements "
                     f"({total * 4 / 2**30:.2f} GiB), identity per array, sizes seed {seed}",
@@ -262,19 +298,34 @@ def batched_compare(torch, shuf, count: int = 10000, seed: int = 2026) -> dict:
         "per_array_Gelem_s": total / t_single / 1e9,
         "speedup": t_single / t_batched,
         "identical_outputs": same,
+        "batched_algorithmic_bytes": call_bytes,
+        "batched_GBs": call_bytes / t_batched / 1e9,
+        "batched_frac_of_hbm_peak": call_bytes / t_batched / 1e9 / HBM_PEAK_GBS,
+        "form": "blocking: level by level in shared launches, default parameters, stream synchronised "
+                "after each tiled level (not graph-capturable)",
+        "async_ms": t_async * 1e3,
+        "async_Gelem_s": total / t_async / 1e9,
+        "async_form": "enqueue-only: first level planned on the device, bounded grids, persistent "
+                      "leaf workgroups with per-class work counters, default parameters",
+        "graph_replay_ms": t_graph * 1e3,
+        "graph_replay_Gelem_s": total / t_graph / 1e9,
+        "async_device_errors": [async_err, graph_err],
+        "speedup_graph_vs_per_array": t_single / t_graph,
     }
 
 
 def serving(torch, shuf, rates, count: int, budget_bytes: int, seed: int = 7) -> list:
-    """Poisson stream of u64 shuffle requests; continuous batching vs one at a time."""
+    """Poisson stream of u64 shuffle requests; continuous batching (the
+    session admits requests by the budget: data plus a workspace bound, or
+    the library's exact workspace when the bound does not fit) against
+    serving one request at a time."""
     import numpy as np
 
     import workloads
 
     w = 8
     sizes = workloads.log_uniform_sizes(count, 10, 26, seed=seed)
-    charge = [int(n) * w * 115 // 100 for n in sizes]  # data plus a workspace allowance
-    # request data stays resident: one buffer per request size class, reused
+    # request data stays resident: one buffer per request
     bufs = [torch.empty(int(n), dtype=torch.int64, device="cuda:0") for n in sizes]
     # warm-up: grow the library's pools with a burst of the largest requests
     big = sorted(range(count), key=lambda j: -int(sizes[j]))[:64]
@@ -294,18 +345,19 @@ def serving(torch, shuf, rates, count: int, budget_bytes: int, seed: int = 7) ->
             lat = np.zeros(count)
             steps = 0
             batch = []
+            queued_max = 0
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if mode == "session":
                 sess = shuf.Session(w)
-                nxt, used, submitted = 0, 0, {}
+                sess.set_budget(budget_bytes)
+                nxt, submitted = 0, {}
                 done_n = 0
                 while done_n < count:
                     now = time.perf_counter() - t0
-                    while nxt < count and arrivals[nxt] <= now and used + charge[nxt] <= budget_bytes:
+                    while nxt < count and arrivals[nxt] <= now:
                         tk = sess.submit(bufs[nxt], int(seeds[nxt]), nxt)
                         submitted[tk] = nxt
-                        used += charge[nxt]
                         nxt += 1
                     inflight = sess.inflight()[0]
                     if inflight == 0:
@@ -315,13 +367,13 @@ def serving(torch, shuf, rates, count: int, budget_bytes: int, seed: int = 7) ->
                                 time.sleep(min(wait, 0.001))
                         continue
                     batch.append(inflight)
+                    queued_max = max(queued_max, sess.queued()[0])
                     done = sess.step()
                     steps += 1
                     tdone = time.perf_counter() - t0
                     for tk in done:
                         j = submitted.pop(tk)
                         lat[j] = tdone - arrivals[j]
-                        used -= charge[j]
                         done_n += 1
                 sess.close()
             else:
@@ -343,10 +395,13 @@ def serving(torch, shuf, rates, count: int, budget_bytes: int, seed: int = 7) ->
                 "elapsed_s": elapsed,
                 "steps": steps,
                 "mean_inflight_per_step": float(np.mean(batch)) if batch else None,
+                "max_queued_by_budget": queued_max if mode == "session" else None,
             })
             print(f"[serve] rate {rate}/s {mode}: p50 {results[-1]['p50_ms']:.2f} ms "
                   f"p99 {results[-1]['p99_ms']:.2f} ms {results[-1]['Gelem_s']:.2f} Gelem/s",
                   file=sys.stderr, flush=True)
+    del bufs
+    torch.cuda.empty_cache()
     return results
 
 
@@ -361,6 +416,9 @@ def main() -> int:
                     help="before the timed region, copy the array once device-to-device (a plain "
                          "copy of known size for scaling HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep of the default line")
+    ap.add_argument("--line-serve-requests", type=int, default=300)
+    ap.add_argument("--line-serve-rates", default="2000,8000,16000")
     ap.add_argument("--serve-rates", default="1000,2000,4000,8000,16000")
     ap.add_argument("--cpu-sample-log2", type=int, default=24)
     ap.add_argument("--cpu-pip-log2", type=int, default=28)
@@ -506,6 +564,20 @@ def main() -> int:
         del t
         torch.cuda.empty_cache()
         line["batched"] = batched_compare(torch, shuf)
+    if not args.no_serving:
+        if "t" in locals():
+            del t
+            torch.cuda.empty_cache()
+        rates = [float(r) for r in args.line_serve_rates.split(",")]
+        sweep = serving(torch, shuf, rates, args.line_serve_requests, 64 << 30)
+        line["serving"] = {
+            "workload": "Poisson stream of in-place shuffles of u64 arrays, sizes log-uniform in "
+                        "[2^10, 2^26], 64 GiB HBM budget admitted by the session (data plus a "
+                        "workspace bound per request, the exact workspace when the bound does not "
+                        "fit), data resident",
+            "requests_per_rate": args.line_serve_requests,
+            "sweep": sweep,
+        }
     if not args.no_cpu_baseline:
         line.update(cpu_baselines(min(args.cpu_sample_log2, log2n), w, min(args.cpu_pip_log2, log2n)))
     line["paper_context"] = PAPER_CONTEXT

@@ -179,6 +179,43 @@ int shuffle_inplace_noalloc(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t
 int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
                     uint64_t seed, void* stream);
 
+/* Enqueue-only form of shuffle_batched (many independent shuffles run
+ * together, Sec. 6.3): the call only launches kernels on `stream` -- no
+ * host synchronisation, no allocation, no memset -- so a caller may capture it
+ * into a HIP graph and replay it.  The first level is planned on the device
+ * from the offsets in DEVICE memory; tile kernels, level tables and the fix-up
+ * run with grids sized from upper bounds (surplus workgroups leave at once);
+ * the leaves run in persistent workgroups that take work from per-size-class
+ * counters.  Array j is shuffled exactly as shuffle_inplace_ex(ptr +
+ * offsets[j] * elem_bytes, offsets[j+1] - offsets[j], elem_bytes, seed, j,
+ * default params), the same as shuffle_batched.
+ *   offsets      DEVICE array of count + 1 non-decreasing element offsets,
+ *                8-byte aligned, read when the kernels run
+ *   count        1 .. 2^22 arrays
+ *   total_elems  an upper bound of offsets[count] (sizes the workspace)
+ *   workspace    device memory of at least shuffle_batched_async_workspace_bytes
+ *                (count, total_elems, elem_bytes) bytes, 256-byte aligned,
+ *                owned by the caller and in use until the stream reaches the
+ *                end of the call's work
+ * Limit: every array holds at most shuffle_batched_async_max_elems(elem_bytes)
+ * elements (one tiled level then leaves subproblems that fit a tile; 2^21 for
+ * 4-byte elements).  Errors detected on the host (before any launch):
+ * SHUF_EINVAL (NULL or misaligned pointers, bad width), SHUF_EUNSUPPORTED
+ * (count or total_elems out of range), SHUF_ENOMEM (workspace too small),
+ * SHUF_EHIP.  Errors detected on the device are reported in the first 4 bytes
+ * of the workspace, to be read after the stream has completed: 0 success;
+ * 32 decreasing offsets, an array above the limit or sizes beyond total_elems
+ * (nothing was moved); 16 a subproblem needed a second tiled level (never
+ * seen in practice at these sizes; the data are then unspecified); 1 or 2 an
+ * index check of the fix-up failed.  The device's first call of the library
+ * runs a short probe that synchronises the stream: make it outside a capture. */
+int shuffle_batched_async(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
+                          uint64_t seed, uint64_t total_elems, void* workspace, uint64_t workspace_bytes,
+                          void* stream);
+int shuffle_batched_async_workspace_bytes(uint64_t count, uint64_t total_elems, uint32_t elem_bytes,
+                                          uint64_t* out_bytes);
+uint64_t shuffle_batched_async_max_elems(uint32_t elem_bytes);
+
 /* One array of a multi-array call or a serving request: n elements at device
  * pointer ptr (aligned to elem_bytes; may be NULL if n <= 1), shuffled with
  * its own seed and stream id. */
@@ -219,7 +256,8 @@ int shuffle_many(const shuf_array_t* arrays, uint64_t count, uint32_t elem_bytes
  *                         calls) if anything is in flight, then report up to
  *                         `cap` completed tickets in done[0..*ndone); further
  *                         completions are reported by later calls
- *   shuf_session_inflight requests submitted and not yet complete, and
+ *   shuf_session_inflight requests submitted and not yet complete (queued
+ *                         ones included), and
  *                         completed tickets not yet reported (may be NULL)
  *   shuf_session_destroy  waits for the session's device and frees the session
  *                         and its device memory (requests still in flight are
@@ -233,6 +271,21 @@ int shuf_session_submit(shuf_session_t* s, const shuf_array_t* a, uint64_t* tick
 int shuf_session_step(shuf_session_t* s, void* stream, uint64_t* done, uint64_t cap,
                       uint64_t* ndone);
 int shuf_session_inflight(const shuf_session_t* s, uint64_t* inflight, uint64_t* completed_unread);
+/* Admission by memory budget (a serving loop's HBM budget; no passage of the
+ * paper).  With a budget of `bytes` (> 0), every submitted request waits in a
+ * queue in submission order and joins the next step only while the charges
+ * of the admitted, unfinished requests fit the budget.  A request is charged
+ * its data bytes plus a workspace bound that needs no GPU work (2 n w + 24 n
+ * + 16 KiB in all); when that does not fit, the exact figure replaces it:
+ * its data plus the workspace the library computes for it alone (the
+ * planning run of shuffle_workspace_bytes, on the null stream).  A request
+ * whose exact charge alone exceeds the budget is refused with SHUF_ENOMEM.
+ * Completed requests release their charges.  Set while the session is idle
+ * (SHUF_EINVAL otherwise); 0 removes the limit.
+ *   shuf_session_queued  requests waiting for admission, and the charges of
+ *                        the admitted ones (may be NULL) */
+int shuf_session_set_budget(shuf_session_t* s, uint64_t bytes);
+int shuf_session_queued(const shuf_session_t* s, uint64_t* queued, uint64_t* used_bytes);
 int shuf_session_destroy(shuf_session_t* s);
 
 /* Free the device pools, pinned host staging and timing events the library

@@ -122,6 +122,10 @@ def lib() -> ctypes.CDLL:
         L.shuf_session_step.restype = i
         L.shuf_session_inflight.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.shuf_session_inflight.restype = i
+        L.shuf_session_set_budget.argtypes = [vp, u64]
+        L.shuf_session_set_budget.restype = i
+        L.shuf_session_queued.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.shuf_session_queued.restype = i
         L.shuf_session_destroy.argtypes = [vp]
         L.shuf_session_destroy.restype = i
         L.shuffle_strerror.argtypes = [i]
@@ -134,6 +138,12 @@ def lib() -> ctypes.CDLL:
         L.shuffle_timing_read.restype = i
         L.shuffle_inplace_noalloc.argtypes = [vp, u64, u32, u64, u32, ctypes.POINTER(_Params), vp]
         L.shuffle_inplace_noalloc.restype = i
+        L.shuffle_batched_async.argtypes = [vp, vp, u64, u32, u64, u64, vp, u64, vp]
+        L.shuffle_batched_async.restype = i
+        L.shuffle_batched_async_workspace_bytes.argtypes = [u64, u64, u32, ctypes.POINTER(u64)]
+        L.shuffle_batched_async_workspace_bytes.restype = i
+        L.shuffle_batched_async_max_elems.argtypes = [u32]
+        L.shuffle_batched_async_max_elems.restype = u64
         L.shuffle_release.argtypes = []
         L.shuffle_release.restype = i
         _lib = L
@@ -249,6 +259,37 @@ def shuffle_inplace_ws(tensor, seed: int, workspace, stream_id: int = 0,
         raise ShuffleError(rc, "shuffle_inplace_ws")
 
 
+def batched_async_workspace_bytes(count: int, total_elems: int, elem_bytes: int) -> int:
+    out = ctypes.c_uint64()
+    rc = lib().shuffle_batched_async_workspace_bytes(count, total_elems, elem_bytes, ctypes.byref(out))
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_batched_async_workspace_bytes")
+    return int(out.value)
+
+
+def batched_async_max_elems(elem_bytes: int) -> int:
+    return int(lib().shuffle_batched_async_max_elems(elem_bytes))
+
+
+def shuffle_batched_async(tensor, offsets, seed: int, workspace, total_elems: int | None = None,
+                          stream=None) -> None:
+    """Enqueue the batched shuffle of `tensor` (rows [offsets[j], offsets[j+1])
+    form array j) on the stream without synchronising: `offsets` is a device
+    int64 tensor of count + 1 entries, `workspace` a device tensor of at least
+    batched_async_workspace_bytes(...) bytes whose first int32 reads 0 after
+    the stream has completed if the device found no error."""
+    n, w = _geometry(tensor)
+    count = offsets.numel() - 1
+    total = n if total_elems is None else int(total_elems)
+    wb = workspace.numel() * workspace.element_size()
+    rc = lib().shuffle_batched_async(
+        ctypes.c_void_p(tensor.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), count, w, seed & (2**64 - 1),
+        total, ctypes.c_void_p(workspace.data_ptr()), wb, _stream_handle(tensor, stream),
+    )
+    if rc != SHUF_OK:
+        raise ShuffleError(rc, "shuffle_batched_async")
+
+
 def shuffle_inplace_noalloc(tensor, seed: int, stream_id: int = 0, params: Params | None = None,
                             stream=None) -> None:
     """shuffle_inplace_ex without any device allocation: every buffer comes
@@ -351,6 +392,21 @@ class Session:
         for t in out:
             self._keep.pop(t, None)
         return out
+
+    def set_budget(self, nbytes: int) -> None:
+        """Admit requests only while the admitted ones' charges (data plus the
+        library's workspace for each) fit `nbytes` (0: no limit)."""
+        rc = lib().shuf_session_set_budget(self._h, int(nbytes))
+        if rc != SHUF_OK:
+            raise ShuffleError(rc, "shuf_session_set_budget")
+
+    def queued(self) -> tuple:
+        """(requests waiting for admission, bytes charged to admitted ones)."""
+        q, u = ctypes.c_uint64(), ctypes.c_uint64()
+        rc = lib().shuf_session_queued(self._h, ctypes.byref(q), ctypes.byref(u))
+        if rc != SHUF_OK:
+            raise ShuffleError(rc, "shuf_session_queued")
+        return int(q.value), int(u.value)
 
     def inflight(self) -> tuple:
         a, b = ctypes.c_uint64(), ctypes.c_uint64()

@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = ["host.hip", "k_rough.hip", "k_count.hip", "k_fixup.hip", "k_leaf.hip"]
+SOURCES = ["host.hip", "k_rough.hip", "k_count.hip", "k_fixup.hip", "k_leaf.hip", "k_plan.hip"]
 LIB = os.path.join(PKG, "libipscshuf.so")
 ARCH = os.environ.get("IPSCSHUF_ARCH", "gfx950")
 

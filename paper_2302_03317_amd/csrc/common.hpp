@@ -241,6 +241,17 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// The workgroup barrier of every kernel here: this wave's LDS operations are
+// complete before it (an explicit lgkmcnt(0) wait), so every LDS write made
+// before the barrier is seen by every wave after it.  The wait is not left to
+// the compiler's own wait placement, which has dropped it before a loop-top
+// barrier (a store of one lane then raced with the other waves' loads).
+__device__ __forceinline__ void block_sync()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // gfx9 encoding of lgkmcnt(0), other counters unchanged
+    __syncthreads();
+}
+
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 

@@ -13,8 +13,10 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "common.hpp"
@@ -451,7 +453,8 @@ struct TimingOff {
     ~TimingOff() { C.timing = was; }
 };
 
-uint64_t engine_submit(Engine& E, uint64_t elem_addr, uint64_t n, uint64_t seed, uint32_t stream_id)
+uint64_t engine_submit(Engine& E, uint64_t elem_addr, uint64_t n, uint64_t seed, uint32_t stream_id,
+                       uint64_t ticket = 0)
 {
     uint32_t slot;
     if (!E.free_slots.empty()) {
@@ -461,7 +464,7 @@ uint64_t engine_submit(Engine& E, uint64_t elem_addr, uint64_t n, uint64_t seed,
         slot = static_cast<uint32_t>(E.ticket.size());
         E.ticket.push_back(0);
     }
-    const uint64_t t = E.next_ticket++;
+    const uint64_t t = ticket ? ticket : E.next_ticket++;
     E.ticket[slot] = t;
     ++E.inflight;
     const uint64_t tile_limit = E.prm.tile - (1u << E.prm.kmax_log2);
@@ -915,6 +918,61 @@ int shuffle_inplace(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t seed, v
     return shuffle_inplace_ex(ptr, n, elem_bytes, seed, 0, &p, stream);
 }
 
+// ---- the enqueue-only batched call ----
+// Workspace layout, all parts 256-byte aligned: a header (error word, level
+// counters, device sizes, work counters, class counts, mover total), then the
+// level's descriptors and tables sized for upper bounds that follow from
+// (count, total_elems), the leaf lists, and the movers' workspace.
+struct AsyncLayout {
+    uint64_t max_tiles, max_chunks, max_buckets, max_leaves, max_tab, max_chtab, nparts;
+    uint64_t header, subs, tile_sub, tile_pofs, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB,
+        wsp, leaves, leaves_cls, big, ws, total;
+};
+constexpr uint64_t kAsyncHeaderBytes = 256;  // err (4) | counters (48) | dsz (32) | qctr (24) | cls (24) | total (8)
+constexpr uint64_t kAsyncMaxCount = 1ull << 22;
+
+AsyncLayout async_layout(uint64_t count, uint64_t total_elems, uint32_t w, const Params& prm)
+{
+    AsyncLayout L{};
+    const uint64_t kmax = 1ull << prm.kmax_log2;
+    L.max_tiles = total_elems / (prm.tile - kmax) + count;
+    L.max_chunks = L.max_tiles / kChunk + count;
+    L.max_buckets = count * kmax;
+    L.max_leaves = count + L.max_buckets;
+    L.max_tab = L.max_tiles * kmax;
+    L.max_chtab = L.max_chunks * kmax;
+    L.nparts = L.max_buckets / kScanChunk + 1;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = off;
+        off += Mem::align(std::max<uint64_t>(bytes, 1));
+        return at;
+    };
+    L.header = take(kAsyncHeaderBytes);
+    L.subs = take(count * sizeof(SubDesc));
+    L.tile_sub = take(L.max_tiles * 4);
+    L.tile_pofs = take(L.max_tiles * 16);
+    L.chunk_sub = take(L.max_chunks * 4);
+    L.bk_sub = take(L.max_buckets * 4);
+    L.cnt = take(L.max_tab * 4);
+    L.mpre = take(L.max_tab * 8);
+    L.kpre = take(L.max_tab * 8);
+    L.chA = take(L.max_chtab * 8);
+    L.chB = take(L.max_chtab * 8);
+    L.N = take(L.max_buckets * 8);
+    L.S = take(L.max_buckets * 8);
+    L.M = take(L.max_buckets * 8);
+    L.K = take(L.max_buckets * 8);
+    L.MB = take(L.max_buckets * 8);
+    L.wsp = take((L.nparts + 2) * 8);
+    L.leaves = take(L.max_leaves * sizeof(LeafDesc));
+    L.leaves_cls = take(3 * L.max_leaves * sizeof(LeafDesc));
+    L.big = take(L.max_buckets * sizeof(LeafDesc));
+    L.ws = take(total_elems * w);
+    L.total = off;
+    return L;
+}
+
 int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
                     uint64_t seed, void* stream)
 {
@@ -941,6 +999,123 @@ int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t
             engine_submit(E, base + offsets[j], offsets[j + 1] - offsets[j], seed,
                           static_cast<uint32_t>(j));
     return engine_drain(E, stream);
+}
+
+int shuffle_batched_async_workspace_bytes(uint64_t count, uint64_t total_elems, uint32_t elem_bytes,
+                                          uint64_t* out_bytes)
+{
+    if (!out_bytes || !valid_width(elem_bytes)) return SHUF_EINVAL;
+    if (count == 0 || count > kAsyncMaxCount || total_elems >= kMaxElements) return SHUF_EUNSUPPORTED;
+    shuf_params_t p;
+    shuf_default_params(0, elem_bytes, &p);
+    *out_bytes = async_layout(count, total_elems, elem_bytes, Params{p.tile, p.kmax_log2, p.n0, p.lmax, 0}).total;
+    return SHUF_OK;
+}
+
+uint64_t shuffle_batched_async_max_elems(uint32_t elem_bytes)
+{
+    if (!valid_width(elem_bytes)) return 0;
+    shuf_params_t p;
+    shuf_default_params(0, elem_bytes, &p);
+    // one tiled level leaves subproblems that fit a tile: kappa covers every
+    // label bit the size needs when (T / 2) * 2^KMAXLOG2 >= n
+    return static_cast<uint64_t>(p.tile / 2) << p.kmax_log2;
+}
+
+int shuffle_batched_async(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
+                          uint64_t seed, uint64_t total_elems, void* workspace, uint64_t workspace_bytes,
+                          void* stream)
+{
+    if (!valid_width(elem_bytes) || !offsets || !workspace) return SHUF_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 || reinterpret_cast<uintptr_t>(offsets) % 8)
+        return SHUF_EINVAL;
+    if (count == 0 || count > kAsyncMaxCount || total_elems >= kMaxElements) return SHUF_EUNSUPPORTED;
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % elem_bytes) return SHUF_EINVAL;
+    shuf_params_t sp;
+    shuf_default_params(0, elem_bytes, &sp);
+    int rc = check_params(&sp, elem_bytes);
+    if (rc != SHUF_OK) return rc;
+    Params prm{sp.tile, sp.kmax_log2, sp.n0, sp.lmax, 0};
+    const AsyncLayout L = async_layout(count, total_elems, elem_bytes, prm);
+    if (workspace_bytes < L.total) return SHUF_ENOMEM;
+    Context* C = current_context();
+    if (!C) return SHUF_EHIP;
+    std::lock_guard<std::mutex> lock(C->mu);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!C->init) {
+        // the device's first call: LDS limits and the lane-order probe (it
+        // synchronises the stream, so it must not happen under capture)
+        HIP_TRY(set_rough_lds_limits());
+        HIP_TRY(set_leaf_lds_limits());
+        bool lane_ordered = false;
+        HIP_TRY(C->probe.ensure(kScratchProbeBytes));
+        HIP_TRY(probe_lds_lane_order(st, static_cast<unsigned long long*>(C->probe.p), &lane_ordered));
+        const char* rank_env = std::getenv("IPSCSHUF_RANK");
+        C->rank_atomic = lane_ordered && !(rank_env && std::strcmp(rank_env, "ballot") == 0);
+        C->init = true;
+        std::call_once(g_exit_hook, [] { std::atexit(release_all); });
+    }
+    prm.rank_atomic = C->rank_atomic ? 1u : 0u;
+    uint8_t* W = static_cast<uint8_t*>(workspace);
+    uint32_t* err = reinterpret_cast<uint32_t*>(W + L.header);
+    unsigned long long* counters = reinterpret_cast<unsigned long long*>(W + L.header + 8);  // 6 words
+    uint64_t* dsz = reinterpret_cast<uint64_t*>(W + L.header + 56);                           // 4 words
+    unsigned long long* qctr = reinterpret_cast<unsigned long long*>(W + L.header + 88);      // 3 words
+    unsigned long long* cls = reinterpret_cast<unsigned long long*>(W + L.header + 112);      // 3 words
+    uint64_t* total = reinterpret_cast<uint64_t*>(W + L.header + 136);
+    const uint64_t kmax = 1ull << prm.kmax_log2;
+    const uint64_t tile_limit = prm.tile - kmax;
+    const uint64_t max_elems = std::min<uint64_t>(shuffle_batched_async_max_elems(elem_bytes), total_elems);
+
+    HIP_TRY(launch_zero_words(err, static_cast<uint32_t>(kAsyncHeaderBytes / 4), st));
+    SubDesc* subs = reinterpret_cast<SubDesc*>(W + L.subs);
+    LeafDesc* leaves = reinterpret_cast<LeafDesc*>(W + L.leaves);
+    HIP_TRY(launch_plan_batched(offsets, count, reinterpret_cast<uintptr_t>(ptr) / elem_bytes, seed, prm,
+                                max_elems, L.max_tiles, L.max_chunks, L.max_buckets, total_elems, subs, leaves,
+                                counters, dsz, err, st));
+    LevelTables T{};
+    T.subs = subs;
+    T.tile_sub = reinterpret_cast<const uint32_t*>(W + L.tile_sub);
+    T.tile_pofs = reinterpret_cast<const uint64_t*>(W + L.tile_pofs);
+    T.chunk_sub = reinterpret_cast<const uint32_t*>(W + L.chunk_sub);
+    T.bk_sub = reinterpret_cast<const uint32_t*>(W + L.bk_sub);
+    T.cnt = reinterpret_cast<uint32_t*>(W + L.cnt);
+    T.mpre = reinterpret_cast<uint64_t*>(W + L.mpre);
+    T.kpre = reinterpret_cast<uint64_t*>(W + L.kpre);
+    T.chA = reinterpret_cast<uint64_t*>(W + L.chA);
+    T.chB = reinterpret_cast<uint64_t*>(W + L.chB);
+    T.N = reinterpret_cast<uint64_t*>(W + L.N);
+    T.S = reinterpret_cast<uint64_t*>(W + L.S);
+    T.M = reinterpret_cast<uint64_t*>(W + L.M);
+    T.K = reinterpret_cast<uint64_t*>(W + L.K);
+    T.MB = reinterpret_cast<uint64_t*>(W + L.MB);
+    T.wsp = reinterpret_cast<uint64_t*>(W + L.wsp);
+    T.total = total;
+    T.err = err;
+    T.ws_cap = total_elems;
+    T.nsubs = count;
+    T.ntiles = L.max_tiles;
+    T.nchunks = L.max_chunks;
+    T.nbuckets = L.max_buckets;
+    T.max_chunks = (max_elems / (prm.tile - kmax) + 1 + kChunk - 1) / kChunk;
+    T.dsz = dsz;
+    HIP_TRY(launch_level_maps(subs, static_cast<uint32_t>(count), L.max_tiles, L.max_chunks, L.max_buckets,
+                              const_cast<uint32_t*>(T.tile_sub), const_cast<uint64_t*>(T.tile_pofs),
+                              const_cast<uint32_t*>(T.chunk_sub), const_cast<uint32_t*>(T.bk_sub), st, dsz));
+    HIP_TRY(launch_rough(elem_bytes, T.subs, T.tile_sub, T.tile_pofs, T.cnt, L.max_tiles, prm, st, dsz));
+    HIP_TRY(launch_tables_sizes(T, st));
+    HIP_TRY(launch_tables_routes(T, st));
+    HIP_TRY(launch_children(T, static_cast<uint32_t>(tile_limit), leaves, reinterpret_cast<LeafDesc*>(W + L.big),
+                            counters, st));
+    HIP_TRY(launch_gather(elem_bytes, W + L.ws, T, st));
+    HIP_TRY(launch_scatter(elem_bytes, W + L.ws, T, st));
+    uint32_t caps[3];
+    leaf_class_caps(elem_bytes, prm, caps);
+    LeafDesc* cls_lists = reinterpret_cast<LeafDesc*>(W + L.leaves_cls);
+    HIP_TRY(launch_leaf_classes(leaves, L.max_leaves, cls_lists, L.max_leaves, caps, cls, st, counters));
+    HIP_TRY(launch_leaf_persistent(elem_bytes, cls_lists, cls, L.max_leaves, prm, caps, qctr, st));
+    HIP_TRY(launch_check_one_level(counters, err, st));
+    return SHUF_OK;
 }
 
 static int check_array(const shuf_array_t& a, uint32_t w)
@@ -975,7 +1150,74 @@ struct shuf_session {
     int device;
     Engine E;
     LeafLists lists;
+    // admission: requests wait in `queue` until their charge (data bytes plus
+    // the workspace the library computes for them alone) fits the budget
+    struct Pending {
+        shuf_array_t a;
+        uint64_t ticket, charge;
+        bool exact;  // charge is the planning run's figure (else the cheap upper bound)
+    };
+    uint64_t budget = 0;  // bytes; 0: no limit
+    uint64_t used = 0;    // charges of admitted, unfinished requests
+    uint64_t next_ticket = 1;
+    uint64_t reported_free = 0;  // entries of E.done_queue whose charges are released
+    std::deque<Pending> queue;
+    std::unordered_map<uint64_t, uint64_t> charge_of;  // admitted ticket -> charge
 };
+
+// The charge of a request: its data plus the device workspace it needs alone.
+// `exact`: the planning run of shuffle_workspace_bytes (counts and tables on
+// the device, no element moves); otherwise an upper bound that needs no GPU
+// work: the movers of a level are at most its items (n * w), and the level
+// tables and lists take less than 24 bytes per item plus 16 KiB.  (A level
+// has at most e n buckets, e = 256 / (T - KMAX), since every subproblem of a
+// tiled level holds more than T - KMAX items, and at most 2 e n (tile,
+// bucket) and (chunk, bucket) entries; at about 236 bytes per bucket (its
+// totals, map entry and child descriptor, and the next step's leaf lists),
+// 20 per (tile, bucket) and 16 per (chunk, bucket) entry that is at most
+// 310 e n bytes, 21 n at the smallest default tile of 4096 items; the 256-byte
+// rounding of about 25 buffers stays below 16 KiB.)
+static int session_charge(const shuf_session_t* s, const shuf_array_t& a, bool exact, uint64_t* out)
+{
+    const uint64_t w = s->E.w;
+    if (a.n <= 1) {
+        *out = a.n * w;
+        return SHUF_OK;
+    }
+    if (!exact) {
+        *out = 2 * a.n * w + 24 * a.n + (16u << 10);
+        return SHUF_OK;
+    }
+    shuf_params_t p;
+    shuf_default_params(a.n, static_cast<uint32_t>(w), &p);
+    uint64_t ws = 0;
+    const int rc = shuffle_workspace_bytes(a.n, static_cast<uint32_t>(w), a.seed, a.stream_id, &p, &ws, nullptr);
+    if (rc != SHUF_OK) return rc;
+    *out = a.n * w + ws;
+    return SHUF_OK;
+}
+
+// Admit queued requests in order while their charges fit the budget; a
+// request whose cheap bound does not fit is charged exactly before it waits.
+static int session_admit(shuf_session_t* s)
+{
+    while (!s->queue.empty()) {
+        shuf_session::Pending& p = s->queue.front();
+        if (s->budget && s->used + p.charge > s->budget) {
+            if (p.exact) break;
+            const int rc = session_charge(s, p.a, true, &p.charge);
+            if (rc != SHUF_OK) return rc;
+            p.exact = true;
+            continue;
+        }
+        engine_submit(s->E, reinterpret_cast<uintptr_t>(p.a.ptr) / s->E.w, p.a.n, p.a.seed, p.a.stream_id,
+                      p.ticket);
+        s->used += p.charge;
+        s->charge_of[p.ticket] = p.charge;
+        s->queue.pop_front();
+    }
+    return SHUF_OK;
+}
 
 int shuf_session_create(uint32_t elem_bytes, shuf_session_t** out)
 {
@@ -998,9 +1240,20 @@ int shuf_session_submit(shuf_session_t* s, const shuf_array_t* a, uint64_t* tick
     const int rc = check_array(*a, s->E.w);
     if (rc != SHUF_OK) return rc;
     if (s->E.ticket.size() >= (1ull << 31) && s->E.free_slots.empty()) return SHUF_EUNSUPPORTED;
-    *ticket = engine_submit(s->E, reinterpret_cast<uintptr_t>(a->ptr) / s->E.w, a->n, a->seed,
-                            a->stream_id);
-    return SHUF_OK;
+    uint64_t charge = 0;
+    bool exact = false;
+    if (s->budget) {
+        int rc2 = session_charge(s, *a, false, &charge);
+        if (rc2 == SHUF_OK && charge > s->budget) {
+            exact = true;
+            rc2 = session_charge(s, *a, true, &charge);
+        }
+        if (rc2 != SHUF_OK) return rc2;
+        if (charge > s->budget) return SHUF_ENOMEM;  // could never be admitted
+    }
+    *ticket = s->next_ticket++;
+    s->queue.push_back({*a, *ticket, charge, exact});
+    return session_admit(s);
 }
 
 int shuf_session_step(shuf_session_t* s, void* stream, uint64_t* done, uint64_t cap,
@@ -1011,6 +1264,8 @@ int shuf_session_step(shuf_session_t* s, void* stream, uint64_t* done, uint64_t 
     Context* C = current_context(&dev);
     if (!C) return SHUF_EHIP;
     if (dev != s->device) return SHUF_EINVAL;
+    int rc0 = session_admit(s);
+    if (rc0 != SHUF_OK) return rc0;
     if (s->E.inflight) {
         std::lock_guard<std::mutex> lock(C->mu);
         C->spans.clear();
@@ -1024,17 +1279,45 @@ int shuf_session_step(shuf_session_t* s, void* stream, uint64_t* done, uint64_t 
         }
         C->stats = st;
     }
+    // completed requests free their charges, and waiting ones may enter
+    for (uint64_t i = s->reported_free; i < s->E.done_queue.size(); ++i) {
+        const auto it = s->charge_of.find(s->E.done_queue[i]);
+        if (it != s->charge_of.end()) {
+            s->used -= it->second;
+            s->charge_of.erase(it);
+        }
+    }
+    s->reported_free = s->E.done_queue.size();
+    rc0 = session_admit(s);
+    if (rc0 != SHUF_OK) return rc0;
     const uint64_t k = std::min<uint64_t>(cap, s->E.done_queue.size());
     for (uint64_t i = 0; i < k; ++i) done[i] = s->E.done_queue[i];
     s->E.done_queue.erase(s->E.done_queue.begin(), s->E.done_queue.begin() + k);
+    s->reported_free -= k;
     *ndone = k;
+    return SHUF_OK;
+}
+
+int shuf_session_set_budget(shuf_session_t* s, uint64_t bytes)
+{
+    if (!s) return SHUF_EINVAL;
+    if (s->E.inflight || !s->queue.empty()) return SHUF_EINVAL;  // only while idle
+    s->budget = bytes;
+    return SHUF_OK;
+}
+
+int shuf_session_queued(const shuf_session_t* s, uint64_t* queued, uint64_t* used_bytes)
+{
+    if (!s || !queued) return SHUF_EINVAL;
+    *queued = s->queue.size();
+    if (used_bytes) *used_bytes = s->used;
     return SHUF_OK;
 }
 
 int shuf_session_inflight(const shuf_session_t* s, uint64_t* inflight, uint64_t* completed_unread)
 {
     if (!s || !inflight) return SHUF_EINVAL;
-    *inflight = s->E.inflight;
+    *inflight = s->E.inflight + s->queue.size();
     if (completed_unread) *completed_unread = s->E.done_queue.size();
     return SHUF_OK;
 }

@@ -39,9 +39,9 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const SubDesc* __restri
         nblk[b] = pc.cap ? static_cast<uint32_t>(((p0 + pc.cap - 1) >> 4) - (p0 >> 4) + 1) : 0u;
         hist[b] = 0;
     }
-    __syncthreads();
+    block_sync();
     if (wv == 0) wave_exclusive_scan(nblk, k);
-    __syncthreads();
+    block_sync();
     const uint32_t nblocks = nblk[k];
     for (uint32_t i = tid; i < nblocks; i += kCountThreads) {
         const uint32_t b = upper_index(nblk, k, i);
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(const SubDesc* __restri
             if (p >= p0 && p < p0 + pcap[b]) atomicAdd(&hist[block_byte(v, j) >> (8 - kappa)], 1u);
         }
     }
-    __syncthreads();
+    block_sync();
     for (uint32_t b = tid; b < k; b += kCountThreads) cnt_tab[sd.tab_off + t * k + b] = hist[b];
 }
 

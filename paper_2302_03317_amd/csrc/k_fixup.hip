@@ -98,6 +98,13 @@ __device__ __forceinline__ uint64_t wave_inclusive_sum64(uint64_t v, uint32_t la
     return v;
 }
 
+// Sizes of the level: the host's, or the device's for a level planned on
+// the device (the launches then cover upper bounds).
+__device__ __forceinline__ uint64_t n_subs(const LevelTables& T) { return T.dsz ? T.dsz[0] : T.nsubs; }
+__device__ __forceinline__ uint64_t n_tiles(const LevelTables& T) { return T.dsz ? T.dsz[1] : T.ntiles; }
+__device__ __forceinline__ uint64_t n_chunks(const LevelTables& T) { return T.dsz ? T.dsz[2] : T.nchunks; }
+__device__ __forceinline__ uint64_t n_buckets(const LevelTables& T) { return T.dsz ? T.dsz[3] : T.nbuckets; }
+
 __device__ __forceinline__ uint64_t chunk_tiles(const SubDesc& sd, uint64_t c, uint64_t* t0)
 {
     *t0 = c * kChunk;
@@ -132,10 +139,15 @@ __global__ __launch_bounds__(kTabThreads) void k_level_maps(const SubDesc* __res
                                                             uint32_t* __restrict__ tile_sub,
                                                             uint64_t* __restrict__ tile_pofs,
                                                             uint32_t* __restrict__ chunk_sub,
-                                                            uint32_t* __restrict__ bk_sub)
+                                                            uint32_t* __restrict__ bk_sub,
+                                                            const uint64_t* __restrict__ dsz)
 {
+    // the index space is [tiles | chunks | buckets] with the host's (upper
+    // bound) sizes; entries beyond the device's sizes are skipped
     uint64_t i = static_cast<uint64_t>(blockIdx.x) * kTabThreads + threadIdx.x;
+    if (dsz) nsub = static_cast<uint32_t>(dsz[0]);
     if (i < ntiles) {
+        if (dsz && i >= dsz[1]) return;
         const uint32_t j = sub_of<0>(subs, nsub, i);
         tile_sub[i] = j;
         // the tile's piece offsets for the two region lengths
@@ -147,17 +159,19 @@ __global__ __launch_bounds__(kTabThreads) void k_level_maps(const SubDesc* __res
     }
     i -= ntiles;
     if (i < nchunks) {
+        if (dsz && i >= dsz[2]) return;
         chunk_sub[i] = sub_of<1>(subs, nsub, i);
         return;
     }
     i -= nchunks;
-    if (i < nbuckets) bk_sub[i] = sub_of<2>(subs, nsub, i);
+    if (i < nbuckets && !(dsz && i >= dsz[3])) bk_sub[i] = sub_of<2>(subs, nsub, i);
 }
 
 // chA[chunk][b] = sum of the chunk's counts of bucket b
 __global__ __launch_bounds__(kTabThreads) void k_chunk_count_sum(LevelTables T)
 {
     const uint64_t g = blockIdx.x;
+    if (g >= n_chunks(T)) return;
     const SubDesc sd = T.subs[T.chunk_sub[g]];
     const uint32_t k = 1u << sd.kappa;
     const uint64_t c = g - sd.chunk_off;
@@ -174,7 +188,7 @@ __global__ __launch_bounds__(kTabThreads) void k_chunk_count_sum(LevelTables T)
 __global__ __launch_bounds__(kTabThreads) void k_bucket_count_total(LevelTables T)
 {
     const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * kTabThreads + threadIdx.x;
-    if (gb >= T.nbuckets) return;
+    if (gb >= n_buckets(T)) return;
     const SubDesc sd = T.subs[T.bk_sub[gb]];
     const uint32_t k = 1u << sd.kappa;
     const uint32_t b = static_cast<uint32_t>(gb - sd.bk_off);
@@ -190,7 +204,7 @@ __global__ __launch_bounds__(kTabThreads) void k_bucket_count_total_wave(LevelTa
 {
     const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * (kTabThreads / 64) + (threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    if (gb >= T.nbuckets) return;  // the whole wave
+    if (gb >= n_buckets(T)) return;  // the whole wave
     const SubDesc sd = T.subs[T.bk_sub[gb]];
     const uint32_t k = 1u << sd.kappa;
     const uint32_t b = static_cast<uint32_t>(gb - sd.bk_off);
@@ -205,6 +219,7 @@ __global__ __launch_bounds__(kTabThreads) void k_bucket_count_total_wave(LevelTa
 // subproblem, each lane a run of consecutive buckets.
 __global__ __launch_bounds__(64) void k_bucket_starts(LevelTables T)
 {
+    if (blockIdx.x >= n_subs(T)) return;
     const SubDesc sd = T.subs[blockIdx.x];
     const uint32_t lane = threadIdx.x;
     const uint32_t k = 1u << sd.kappa;
@@ -225,6 +240,7 @@ __global__ __launch_bounds__(64) void k_bucket_starts(LevelTables T)
 __global__ __launch_bounds__(kTabThreads) void k_chunk_route_sum(LevelTables T)
 {
     const uint64_t g = blockIdx.x;
+    if (g >= n_chunks(T)) return;
     const SubDesc sd = T.subs[T.chunk_sub[g]];
     const uint32_t k = 1u << sd.kappa;
     const uint64_t c = g - sd.chunk_off;
@@ -249,7 +265,7 @@ __global__ __launch_bounds__(kTabThreads) void k_chunk_route_sum(LevelTables T)
 __global__ __launch_bounds__(kTabThreads) void k_bucket_route_scan(LevelTables T)
 {
     const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * kTabThreads + threadIdx.x;
-    if (gb >= T.nbuckets) return;
+    if (gb >= n_buckets(T)) return;
     const SubDesc sd = T.subs[T.bk_sub[gb]];
     const uint32_t k = 1u << sd.kappa;
     const uint32_t b = static_cast<uint32_t>(gb - sd.bk_off);
@@ -272,7 +288,7 @@ __global__ __launch_bounds__(kTabThreads) void k_bucket_route_scan_wave(LevelTab
 {
     const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * (kTabThreads / 64) + (threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    if (gb >= T.nbuckets) return;  // the whole wave
+    if (gb >= n_buckets(T)) return;  // the whole wave
     const SubDesc sd = T.subs[T.bk_sub[gb]];
     const uint32_t k = 1u << sd.kappa;
     const uint32_t b = static_cast<uint32_t>(gb - sd.bk_off);
@@ -308,13 +324,14 @@ __global__ __launch_bounds__(kTabThreads) void k_ws_chunk_sums(LevelTables T)
     __shared__ uint64_t part[kTabThreads];
     const uint64_t c0 = static_cast<uint64_t>(blockIdx.x) * kScanChunk;
     uint64_t s = 0;
-    for (uint64_t i = c0 + threadIdx.x; i < c0 + kScanChunk && i < T.nbuckets; i += kTabThreads)
+    const uint64_t nb = n_buckets(T);
+    for (uint64_t i = c0 + threadIdx.x; i < c0 + kScanChunk && i < nb; i += kTabThreads)
         s += T.M[i];
     part[threadIdx.x] = s;
-    __syncthreads();
+    block_sync();
     for (uint32_t d = kTabThreads / 2; d > 0; d >>= 1) {
         if (threadIdx.x < d) part[threadIdx.x] += part[threadIdx.x + d];
-        __syncthreads();
+        block_sync();
     }
     if (threadIdx.x == 0) T.wsp[blockIdx.x] = part[0];
 }
@@ -336,11 +353,12 @@ __global__ __launch_bounds__(kTabThreads) void k_ws_chunk_scan(LevelTables T)
     constexpr uint32_t per = kScanChunk / kTabThreads;  // consecutive buckets per thread
     __shared__ uint64_t part[kTabThreads];
     const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * kScanChunk + threadIdx.x * per;
+    const uint64_t nb = n_buckets(T);
     uint64_t s = 0;
     for (uint32_t j = 0; j < per; ++j)
-        if (b0 + j < T.nbuckets) s += T.M[b0 + j];
+        if (b0 + j < nb) s += T.M[b0 + j];
     part[threadIdx.x] = s;
-    __syncthreads();
+    block_sync();
     if (threadIdx.x == 0) {
         uint64_t run = T.wsp[blockIdx.x];
         for (uint32_t i = 0; i < kTabThreads; ++i) {
@@ -349,10 +367,10 @@ __global__ __launch_bounds__(kTabThreads) void k_ws_chunk_scan(LevelTables T)
             run += v;
         }
     }
-    __syncthreads();
+    block_sync();
     uint64_t run = part[threadIdx.x];
     for (uint32_t j = 0; j < per; ++j) {
-        if (b0 + j < T.nbuckets) {
+        if (b0 + j < nb) {
             const uint64_t v = T.M[b0 + j];
             T.MB[b0 + j] = run;
             run += v;
@@ -364,6 +382,7 @@ __global__ __launch_bounds__(kTabThreads) void k_ws_chunk_scan(LevelTables T)
 __global__ __launch_bounds__(kTabThreads) void k_chunk_route_prefix(LevelTables T)
 {
     const uint64_t g = blockIdx.x;
+    if (g >= n_chunks(T)) return;
     const SubDesc sd = T.subs[T.chunk_sub[g]];
     const uint32_t k = 1u << sd.kappa;
     const uint64_t c = g - sd.chunk_off;
@@ -402,7 +421,7 @@ __global__ __launch_bounds__(kChildThreads) void k_children(LevelTables T, uint3
     const uint64_t gb = static_cast<uint64_t>(blockIdx.x) * kChildThreads + threadIdx.x;
     uint64_t n = 0;
     LeafDesc c{};
-    if (gb < T.nbuckets) {
+    if (gb < n_buckets(T)) {
         const SubDesc sd = T.subs[T.bk_sub[gb]];
         n = T.N[gb];
         c = LeafDesc{sd.elem_off, sd.base + T.S[gb], n, sd.seed, sd.level + 1, sd.stream_id,
@@ -418,7 +437,7 @@ __global__ __launch_bounds__(kChildThreads) void k_children(LevelTables T, uint3
         wcnt[1][wv] = static_cast<uint32_t>(__popcll(mb));
         wcnt[2][wv] = sum;
     }
-    __syncthreads();
+    block_sync();
     if (threadIdx.x == 0) {
         unsigned long long nl = 0, nb = 0, ne = 0;
         for (uint32_t w = 0; w < kW; ++w) {
@@ -436,7 +455,7 @@ __global__ __launch_bounds__(kChildThreads) void k_children(LevelTables T, uint3
             wbase[1][w] += bb;
         }
     }
-    __syncthreads();
+    block_sync();
     if (leaf) leaves[wbase[0][wv] + bits_below(ml)] = c;
     if (more) big[wbase[1][wv] + bits_below(mb)] = c;
 }
@@ -449,7 +468,9 @@ __global__ __launch_bounds__(kTabThreads) void k_gather(E* __restrict__ ws, Leve
     __shared__ uint32_t fill[kKmax], kept[kKmax], disp[kKmax];
     __shared__ uint32_t ovt[kKmax + 1], hot[kKmax + 1], outt[kKmax + 1];
     const uint32_t tid = threadIdx.x, wv = tid >> 6;
-    const uint64_t g = xcd_order(blockIdx.x, gridDim.x);
+    const uint64_t nt = n_tiles(T);
+    if (blockIdx.x >= nt) return;
+    const uint64_t g = xcd_order(blockIdx.x, static_cast<uint32_t>(nt));
     const SubDesc sd = T.subs[T.tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
     const uint32_t k = 1u << sd.kappa;
@@ -469,11 +490,11 @@ __global__ __launch_bounds__(kTabThreads) void k_gather(E* __restrict__ ws, Leve
         outt[b] = static_cast<uint32_t>(st.disp + st.ov);
         base_w[b] = T.MB[gb] + T.mpre[e];
     }
-    __syncthreads();
+    block_sync();
     if (wv == 0) wave_exclusive_scan(ovt, k);
     if (wv == 1) wave_exclusive_scan(hot, k);
     if (wv == 2) wave_exclusive_scan(outt, k);
-    __syncthreads();
+    block_sync();
     const uint32_t nout = outt[k];
     for (uint32_t i = tid; i < nout; i += kTabThreads) {
         const uint32_t b = upper_index(outt, k, i);
@@ -506,7 +527,9 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ w
     __shared__ uint64_t S[kKmax], Ktot[kKmax], MB[kKmax], lo[kKmax], kept_lo[kKmax], kpre[kKmax];
     __shared__ uint32_t kept[kKmax], nkt[kKmax + 1];
     const uint32_t tid = threadIdx.x, wv = tid >> 6;
-    const uint64_t g = xcd_order(blockIdx.x, gridDim.x);
+    const uint64_t nt = n_tiles(T);
+    if (blockIdx.x >= nt) return;
+    const uint64_t g = xcd_order(blockIdx.x, static_cast<uint32_t>(nt));
     const SubDesc sd = T.subs[T.tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
     const uint32_t k = 1u << sd.kappa;
@@ -525,9 +548,9 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ w
         kpre[b] = T.kpre[e];
         nkt[b] = static_cast<uint32_t>(st.cap - st.kept);
     }
-    __syncthreads();
+    block_sync();
     if (wv == 0) wave_exclusive_scan(nkt, k);
-    __syncthreads();
+    block_sync();
     const uint32_t nfree = nkt[k];
     for (uint32_t i = tid; i < nfree; i += kTabThreads) {
         const uint32_t b = upper_index(nkt, k, i);  // piece of the free slot
@@ -560,13 +583,14 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ w
 
 hipError_t launch_level_maps(const SubDesc* subs, uint32_t nsub, uint64_t ntiles, uint64_t nchunks,
                              uint64_t nbuckets, uint32_t* tile_sub, uint64_t* tile_pofs,
-                             uint32_t* chunk_sub, uint32_t* bk_sub, hipStream_t stream)
+                             uint32_t* chunk_sub, uint32_t* bk_sub, hipStream_t stream,
+                             const uint64_t* dsz)
 {
     const uint64_t n = ntiles + nchunks + nbuckets;
     if (n == 0 || nsub == 0) return hipSuccess;
     hipLaunchKernelGGL(k_level_maps, dim3(static_cast<uint32_t>((n + kTabThreads - 1) / kTabThreads)),
                        dim3(kTabThreads), 0, stream, subs, nsub, ntiles, nchunks, nbuckets, tile_sub,
-                       tile_pofs, chunk_sub, bk_sub);
+                       tile_pofs, chunk_sub, bk_sub, dsz);
     return hipGetLastError();
 }
 

@@ -10,6 +10,8 @@
 // wave each.  Segments at the base case run Fisher-Yates, one lane per
 // segment.  Finally the elements are read once from HBM into an LDS staging
 // copy and written once, every position gathering its item by the index array.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "rng.hpp"
@@ -94,7 +96,7 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
     const uint32_t rounds = per_wave / 64;
     const uint32_t first_x = s0 + wv * per_wave + lane;
     for (uint32_t j = tid; j < (kWaves + 1) * hs; j += kThreads) H[j] = 0;
-    __syncthreads();
+    block_sync();
     uint32_t pk[ROUNDS];
     uint32_t lb[(ROUNDS + 3) / 4];
 #pragma unroll
@@ -119,7 +121,7 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
         if (r % 4 == 0) lb[r / 4] = l;
         else lb[r / 4] |= l << (8 * (r % 4));
     }
-    __syncthreads();
+    block_sync();
     for (uint32_t l = tid; l < k; l += kThreads) {
         uint32_t run = 0;
         for (int w = 0; w < kWaves; ++w) {
@@ -129,15 +131,15 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
         }
         Htot[l] = run;
     }
-    __syncthreads();
+    block_sync();
     if (wv == 0) wave_exclusive_scan(Htot, k);
-    __syncthreads();
+    block_sync();
     for (uint32_t l = tid; l < k; l += kThreads) {
         const uint32_t base = s0 + Htot[l];
         out[l] = seg_pack(base, Htot[l + 1] - Htot[l]);
         for (int w = 0; w < kWaves; ++w) H[w * hs + l] += base;
     }
-    __syncthreads();
+    block_sync();
 #pragma unroll
     for (uint32_t r = 0; r < static_cast<uint32_t>(ROUNDS); ++r) {
         const uint32_t x = first_x + 64u * r;
@@ -146,7 +148,7 @@ __device__ __forceinline__ void split_workgroup(uint16_t* idx, const uint8_t* la
             idx[H[wv * hs + l] + (pk[r] >> 16)] = static_cast<uint16_t>(pk[r]);
         }
     }
-    __syncthreads();
+    block_sync();
 }
 
 // One wave's stable split of segment [s0, s0 + len), len <= 64 * ROUNDS
@@ -196,18 +198,15 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
     }
 }
 
-// One size class of leaves: at most kThreads * ROUNDS items each, LDS laid
-// out for the class capacity `cap`, MINW waves per SIMD.
-template <typename E, int ROUNDS, int MINW>
-__global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restrict__ leaves,
-                                                         Params prm, uint32_t cap)
+// One leaf of a size class: at most kThreads * ROUNDS items, LDS laid out
+// for the class capacity `cap` at smem.  Called by the whole workgroup.
+template <typename E, int ROUNDS>
+__device__ __forceinline__ void leaf_body(const LeafDesc ld, const Params& prm, uint32_t cap, uint8_t* smem)
 {
     constexpr int EMAX = ROUNDS;
     constexpr uint32_t kWaveSegMax = 64u * ROUNDS;  // largest segment split by one wave
-    extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const uint32_t wv = uniform(tid >> 6);  // the same in all lanes of a wave
-    const LeafDesc ld = leaves[xcd_order(blockIdx.x, gridDim.x)];
     const uint32_t m = static_cast<uint32_t>(ld.m);
     const uint32_t kmax = 1u << prm.kmax_log2;
     const uint32_t hs = kmax + 1;  // row stride of the counters
@@ -252,7 +251,7 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
     }
     bool classified = true;
     for (;;) {
-        __syncthreads();
+        block_sync();
         const uint32_t nseg = misc[0];
         if (nseg == 0) break;
         const bool first = level == ld.level;  // the single segment [0, m) in its initial order
@@ -267,7 +266,7 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
                 misc[1] = 0;
                 misc[2] = 0;
             }
-            __syncthreads();
+            block_sync();
             for (uint32_t i = tid; i < nseg; i += kThreads) {
                 const uint32_t len = seg_len(cur[i]);
                 uint32_t kk = 0;
@@ -282,9 +281,9 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
                 }
                 tmpk[i] = kk;
             }
-            __syncthreads();
+            block_sync();
             if (wv == 0) wave_exclusive_scan(H, 256);
-            __syncthreads();
+            block_sync();
             for (uint32_t i = tid; i < nseg; i += kThreads) {
                 const uint32_t e = cur[i];
                 const uint32_t len = seg_len(e);
@@ -292,7 +291,7 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
                     nxt[atomicAdd(&H[255 - (len < 255 ? len : 255)], 1u)] = e;
             }
             if (tid == 0) misc[3] = H[256];
-            __syncthreads();
+            block_sync();
         }
         classified = false;
         const uint32_t nbig = misc[1], nwave = misc[2], nfy = misc[3];
@@ -310,9 +309,9 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
                 *reinterpret_cast<uint4*>(labraw + 16 * i) = make_uint4(v.x, v.y, v.z, v.w);
             }
         }
-        __syncthreads();
+        block_sync();
         if (wv == 0) wave_exclusive_scan(tmpk, nseg);  // child offsets; tmpk[nseg] = total
-        __syncthreads();
+        block_sync();
 
         // Large segments: the whole workgroup, one segment at a time.
         for (uint32_t bi = 0; bi < nbig; ++bi) {
@@ -376,14 +375,14 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
                 }
             }
         }
-        __syncthreads();
+        block_sync();
         if (tid == 0) misc[0] = tmpk[nseg];
         uint32_t* sw = cur;
         cur = nxt;
         nxt = sw;
         ++level;
     }
-    __syncthreads();
+    block_sync();
 
     // idx[x] is the leaf index of the item that ends at x.  The elements come
     // from HBM straight into the staging copy (over the dead index arrays),
@@ -394,7 +393,7 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
         const uint32_t x = r * kThreads + tid;
         if (x < m) src[r] = idx[x];
     }
-    __syncthreads();
+    block_sync();
     {
         const uint32_t nw = m * static_cast<uint32_t>(sizeof(E) / 4);
         const global_t<uint32_t>* from = reinterpret_cast<const global_t<uint32_t>*>(X);
@@ -404,11 +403,42 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restr
         }
         __builtin_amdgcn_s_waitcnt(0);
     }
-    __syncthreads();
+    block_sync();
 #pragma unroll
     for (int r = 0; r < EMAX; ++r) {
         const uint32_t x = r * kThreads + tid;
         if (x < m) X[x] = stage[src[r]];
+    }
+}
+
+// One size class of leaves, one workgroup per leaf, MINW waves per SIMD.
+template <typename E, int ROUNDS, int MINW>
+__global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restrict__ leaves,
+                                                         Params prm, uint32_t cap)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    leaf_body<E, ROUNDS>(leaves[xcd_order(blockIdx.x, gridDim.x)], prm, cap, smem);
+}
+
+// The same with persistent workgroups: each takes the next leaf of the class
+// from the work counter *qctr until *count leaves are taken.
+template <typename E, int ROUNDS, int MINW>
+__global__ __launch_bounds__(kThreads, MINW) void k_leaf_persistent(const LeafDesc* __restrict__ leaves,
+                                                                    const unsigned long long* __restrict__ count,
+                                                                    unsigned long long* __restrict__ qctr,
+                                                                    Params prm, uint32_t cap)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ unsigned long long take;
+    const unsigned long long total = *count;
+    for (;;) {
+        if (threadIdx.x == 0) take = atomicAdd(qctr, 1ull);
+        block_sync();
+        const unsigned long long i = take;
+        block_sync();  // every thread has read it before the next take
+        if (i >= total) break;
+        leaf_body<E, ROUNDS>(leaves[i], prm, cap, smem);
+        block_sync();  // the next leaf reuses the LDS
     }
 }
 
@@ -470,6 +500,41 @@ hipError_t leaf_t(const LeafDesc* leaves, const uint64_t* count, uint64_t stride
     return leaf_class_t<E, LC::kRoundsL, 4>(leaves + 2 * stride, count[2], prm, caps[2], stream);
 }
 
+template <typename E, int ROUNDS, int MINW>
+hipError_t leaf_class_persistent_t(const LeafDesc* leaves, const unsigned long long* count,
+                                   unsigned long long* qctr, const Params& prm, uint32_t cap,
+                                   hipStream_t stream)
+{
+    if (cap > static_cast<uint32_t>(ROUNDS) * kThreads) return hipErrorInvalidValue;
+    const LeafLayout LL = leaf_layout(cap, sizeof(E), 1u << prm.kmax_log2, prm.n0);
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(&k_leaf_persistent<E, ROUNDS, MINW>), kThreads, LL.total);
+    if (e != hipSuccess) return e;
+    const uint32_t grid = static_cast<uint32_t>(std::max(1, cus) * std::max(1, per_cu));
+    hipLaunchKernelGGL((k_leaf_persistent<E, ROUNDS, MINW>), dim3(grid), dim3(kThreads), LL.total, stream,
+                       leaves, count, qctr, prm, cap);
+    return hipGetLastError();
+}
+
+template <typename E>
+hipError_t leaf_persistent_t(const LeafDesc* leaves, const unsigned long long* count, uint64_t stride,
+                             const Params& prm, const uint32_t* caps, unsigned long long* qctr,
+                             hipStream_t stream)
+{
+    using LC = LeafClasses<E>;
+    hipError_t e;
+    e = leaf_class_persistent_t<E, LC::kRoundsS, 8>(leaves, count, qctr, prm, caps[0], stream);
+    if (e != hipSuccess) return e;
+    e = leaf_class_persistent_t<E, LC::kRoundsM, 6>(leaves + stride, count + 1, qctr + 1, prm, caps[1], stream);
+    if (e != hipSuccess) return e;
+    return leaf_class_persistent_t<E, LC::kRoundsL, 4>(leaves + 2 * stride, count + 2, qctr + 2, prm, caps[2],
+                                                       stream);
+}
+
 // Sort leaves into the three classes (order inside a class is immaterial:
 // every leaf is finished independently).
 constexpr int kClassThreads = 1024;
@@ -478,8 +543,10 @@ __global__ __launch_bounds__(kClassThreads) void k_leaf_classes(const LeafDesc* 
                                                                 uint64_t n, LeafDesc* __restrict__ out,
                                                                 uint64_t stride, uint32_t cap_s,
                                                                 uint32_t cap_m,
-                                                                unsigned long long* __restrict__ count)
+                                                                unsigned long long* __restrict__ count,
+                                                                const unsigned long long* __restrict__ dn)
 {
+    if (dn) n = *dn;  // the device's leaf count (the grid covers an upper bound)
     // Slots are reserved with one atomic per class and workgroup: the waves'
     // counts are added up in LDS.  No early exit: every thread takes part in
     // the barriers.
@@ -500,7 +567,7 @@ __global__ __launch_bounds__(kClassThreads) void k_leaf_classes(const LeafDesc* 
         mask[k] = __ballot(c == k);
         if (lane == 0) wcnt[k][wv] = static_cast<uint32_t>(__popcll(mask[k]));
     }
-    __syncthreads();
+    block_sync();
     if (threadIdx.x < 3) {
         const uint32_t k = threadIdx.x;
         unsigned long long run = 0;
@@ -511,7 +578,7 @@ __global__ __launch_bounds__(kClassThreads) void k_leaf_classes(const LeafDesc* 
         const unsigned long long b = run ? atomicAdd(&count[k], run) : 0ull;
         for (uint32_t w = 0; w < kW; ++w) wbase[k][w] += b;
     }
-    __syncthreads();
+    block_sync();
     if (c < 3) out[c * stride + wbase[c][wv] + bits_below(mask[c])] = d;
 }
 
@@ -544,12 +611,25 @@ void leaf_class_caps(uint32_t w, const Params& prm, uint32_t* caps)
 }
 
 hipError_t launch_leaf_classes(const LeafDesc* in, uint64_t n, LeafDesc* out, uint64_t stride,
-                               const uint32_t* caps, unsigned long long* count, hipStream_t stream)
+                               const uint32_t* caps, unsigned long long* count, hipStream_t stream,
+                               const unsigned long long* dn)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_leaf_classes, dim3(static_cast<uint32_t>((n + kClassThreads - 1) / kClassThreads)),
-                       dim3(kClassThreads), 0, stream, in, n, out, stride, caps[0], caps[1], count);
+                       dim3(kClassThreads), 0, stream, in, n, out, stride, caps[0], caps[1], count, dn);
     return hipGetLastError();
+}
+
+hipError_t launch_leaf_persistent(uint32_t w, const LeafDesc* leaves, const unsigned long long* dcount,
+                                  uint64_t stride, const Params& prm, const uint32_t* caps,
+                                  unsigned long long* qctr, hipStream_t stream)
+{
+    switch (w) {
+    case 4: return leaf_persistent_t<uint32_t>(leaves, dcount, stride, prm, caps, qctr, stream);
+    case 8: return leaf_persistent_t<uint64_t>(leaves, dcount, stride, prm, caps, qctr, stream);
+    case 16: return leaf_persistent_t<Elem16>(leaves, dcount, stride, prm, caps, qctr, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_leaf(uint32_t w, const LeafDesc* leaves, const uint64_t* count, uint64_t stride,
@@ -568,6 +648,15 @@ static hipError_t leaf_limits_t()
 {
     using LC = LeafClasses<E>;
     hipError_t e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsS, 8>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax - 64);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsM, 6>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax - 64);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsL, 4>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax - 64);
+    if (e != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<E, LC::kRoundsS, 8>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
     if (e != hipSuccess) return e;

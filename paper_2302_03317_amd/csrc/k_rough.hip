@@ -155,12 +155,17 @@ template <typename E, int R>
 __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __restrict__ subs,
                                                     const uint32_t* __restrict__ tile_sub,
                                                     const uint64_t* __restrict__ tile_pofs,
-                                                    uint32_t* __restrict__ cnt_tab, Params prm)
+                                                    uint32_t* __restrict__ cnt_tab, Params prm,
+                                                    const uint64_t* __restrict__ dsz)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const uint32_t wv = uniform(tid >> 6);  // the same in all lanes of a wave
-    const uint64_t g = xcd_order(blockIdx.x, gridDim.x);
+    // tiles of the level: the grid, or the device's count for a level planned
+    // on the device (the grid then covers an upper bound)
+    const uint32_t ntl = dsz ? static_cast<uint32_t>(dsz[1]) : gridDim.x;
+    if (blockIdx.x >= ntl) return;
+    const uint64_t g = xcd_order(blockIdx.x, ntl);
     const SubDesc sd = subs[tile_sub[g]];
     const uint64_t t = g - sd.tile_off;
     const uint32_t kappa = sd.kappa, k = 1u << kappa;
@@ -246,7 +251,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
         }
     }
     __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    block_sync();
 
     // Wave wv owns read-order slots [wv * 64R, (wv + 1) * 64R); round r gives
     // lane l the slot wv * 64R + 64r + l.
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
         const uint32_t q = first + 64u * r;
         data.set(r, stage[q < ts ? q : 0u]);
     }
-    __syncthreads();  // staging is free: labels and per-wave counters overlay it
+    block_sync();  // staging is free: labels and per-wave counters overlay it
 
     // Labels in staging order: block i of the tile belongs to piece
     // bpiece[i]; d is the offset of its first position from the piece start.
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
         }
     }
     for (uint32_t i = tid; i < kRoughWaves * hs; i += kRoughThreads) H[i] = 0;
-    __syncthreads();
+    block_sync();
 
     uint32_t pk[R];
     uint32_t* Hw = H + wv * hs;
@@ -330,7 +335,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
         default: rank_rounds<8, R>(lab, Hw, first, ts, pk); break;
         }
     }
-    __syncthreads();
+    block_sync();
 
     // Per label: offsets of the waves, the tile's count, fill, overflow, holes.
     for (uint32_t l = tid; l < k; l += kRoughThreads) {
@@ -346,10 +351,10 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
         ovt[l] = run - f;
         hot[l] = cap[l] - f;
     }
-    __syncthreads();
+    block_sync();
     if (wv == 0) wave_exclusive_scan(ovt, k);
     if (wv == 1) wave_exclusive_scan(hot, k);
-    __syncthreads();
+    block_sync();
 
     // Free slots of the pieces, in order, as a list (the label area is dead),
     // and the slot table of every (wave, label): an item of rank rr within
@@ -372,7 +377,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
         WT[w * k + l] = make_uint2((A & 0xFFFFu) | (static_cast<uint32_t>(B) << 16),
                                    ovt[l] - static_cast<uint32_t>(B));
     }
-    __syncthreads();
+    block_sync();
 
     // Destination slot in staging order.
     if (use_list) {
@@ -409,13 +414,13 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
             }
         }
     }
-    __syncthreads();  // labels, free list and counters are dead from here on
+    block_sync();  // labels, free list and counters are dead from here on
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t q = first + 64u * r;
         if (q < ts) stage[pk[r]] = data.get(r);
     }
-    __syncthreads();
+    block_sync();
 
     // Staging -> pieces, one contiguous run each.
     {
@@ -432,13 +437,14 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
 
 template <typename E>
 hipError_t launch_rough_t(const SubDesc* subs, const uint32_t* tile_sub, const uint64_t* tile_pofs,
-                          uint32_t* cnt_tab, uint64_t ntiles, const Params& prm, hipStream_t stream)
+                          uint32_t* cnt_tab, uint64_t ntiles, const Params& prm, hipStream_t stream,
+                          const uint64_t* dsz)
 {
     constexpr int R = static_cast<int>(kTileBytesMax / (sizeof(E) * kRoughThreads));
     const RoughLayout L = rough_layout(prm.tile, sizeof(E), 1u << prm.kmax_log2);
     if (ntiles == 0) return hipSuccess;
     hipLaunchKernelGGL((k_rough<E, R>), dim3(static_cast<uint32_t>(ntiles)), dim3(kRoughThreads),
-                       L.total, stream, subs, tile_sub, tile_pofs, cnt_tab, prm);
+                       L.total, stream, subs, tile_sub, tile_pofs, cnt_tab, prm, dsz);
     return hipGetLastError();
 }
 
@@ -446,12 +452,12 @@ hipError_t launch_rough_t(const SubDesc* subs, const uint32_t* tile_sub, const u
 
 hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_sub,
                         const uint64_t* tile_pofs, uint32_t* cnt_tab, uint64_t ntiles,
-                        const Params& prm, hipStream_t stream)
+                        const Params& prm, hipStream_t stream, const uint64_t* dsz)
 {
     switch (w) {
-    case 4: return launch_rough_t<uint32_t>(subs, tile_sub, tile_pofs, cnt_tab, ntiles, prm, stream);
-    case 8: return launch_rough_t<uint64_t>(subs, tile_sub, tile_pofs, cnt_tab, ntiles, prm, stream);
-    case 16: return launch_rough_t<Elem16>(subs, tile_sub, tile_pofs, cnt_tab, ntiles, prm, stream);
+    case 4: return launch_rough_t<uint32_t>(subs, tile_sub, tile_pofs, cnt_tab, ntiles, prm, stream, dsz);
+    case 8: return launch_rough_t<uint64_t>(subs, tile_sub, tile_pofs, cnt_tab, ntiles, prm, stream, dsz);
+    case 16: return launch_rough_t<Elem16>(subs, tile_sub, tile_pofs, cnt_tab, ntiles, prm, stream, dsz);
     default: return hipErrorInvalidValue;
     }
 }

@@ -18,7 +18,7 @@ using Elem16 = uint4;
 // Rough pass of one tiled level: one workgroup per tile.
 hipError_t launch_rough(uint32_t w, const SubDesc* subs, const uint32_t* tile_sub,
                         const uint64_t* tile_pofs, uint32_t* cnt_tab, uint64_t ntiles,
-                        const Params& prm, hipStream_t stream);
+                        const Params& prm, hipStream_t stream, const uint64_t* dsz = nullptr);
 hipError_t set_rough_lds_limits();
 // Whether one wave's same-address LDS atomic adds return in lane order on the
 // current device (a probe kernel over random label patterns, run once);
@@ -51,6 +51,11 @@ struct LevelTables {
     uint64_t ws_cap;            // workspace elements available to gather / scatter
     uint64_t nsubs, ntiles, nchunks, nbuckets;
     uint64_t max_chunks;        // most chunks of one subproblem
+    // For a level planned on the device: its sizes {nsubs, ntiles, nchunks,
+    // nbuckets} in device memory, the host's fields above then being upper
+    // bounds that size the launches (blocks beyond the device's sizes leave
+    // at once).  NULL for a level planned on the host.
+    const uint64_t* dsz;
 };
 
 constexpr uint32_t kScanChunk = 4096;  // buckets per block of the workspace scan
@@ -67,7 +72,8 @@ hipError_t launch_children(const LevelTables& t, uint32_t tile_limit, LeafDesc* 
 // every tile's two piece offsets (see TilePieces).
 hipError_t launch_level_maps(const SubDesc* subs, uint32_t nsub, uint64_t ntiles, uint64_t nchunks,
                              uint64_t nbuckets, uint32_t* tile_sub, uint64_t* tile_pofs,
-                             uint32_t* chunk_sub, uint32_t* bk_sub, hipStream_t stream);
+                             uint32_t* chunk_sub, uint32_t* bk_sub, hipStream_t stream,
+                             const uint64_t* dsz = nullptr);
 
 // Counts -> final sizes and starts; movers, kept prefixes; workspace bases.
 hipError_t launch_tables_sizes(const LevelTables& t, hipStream_t stream);
@@ -80,12 +86,29 @@ hipError_t launch_scatter(uint32_t w, const uint8_t* ws, const LevelTables& t,
 // Subproblems that fit a tile: in-LDS levels and Fisher-Yates, launched per
 // size class (small, medium, large: caps[0..2] items, LDS sized to match).
 void leaf_class_caps(uint32_t w, const Params& prm, uint32_t* caps);
+// (dn: the leaf count in device memory, n then being an upper bound)
 hipError_t launch_leaf_classes(const LeafDesc* in, uint64_t n, LeafDesc* out, uint64_t stride,
-                               const uint32_t* caps, unsigned long long* count, hipStream_t stream);
+                               const uint32_t* caps, unsigned long long* count, hipStream_t stream,
+                               const unsigned long long* dn = nullptr);
 // leaves of class c are leaves[c * stride, c * stride + count[c])
 hipError_t launch_leaf(uint32_t w, const LeafDesc* leaves, const uint64_t* count, uint64_t stride,
                        const Params& prm, const uint32_t* caps, hipStream_t stream);
+// The same with the class counts in device memory (dcount[0..2]): persistent
+// workgroups, as many as the device holds at once, take leaves from the
+// per-class work counters qctr[0..2] (zero on entry) until none are left.
+hipError_t launch_leaf_persistent(uint32_t w, const LeafDesc* leaves, const unsigned long long* dcount,
+                                  uint64_t stride, const Params& prm, const uint32_t* caps,
+                                  unsigned long long* qctr, hipStream_t stream);
 hipError_t set_leaf_lds_limits();
+// Device planning of a batched call's first level (see k_plan.hip), and two
+// small helpers of the enqueue-only batched call.
+hipError_t launch_plan_batched(const uint64_t* offsets, uint64_t count, uint64_t elem_base, uint64_t seed,
+                               const Params& prm, uint64_t max_elems, uint64_t max_tiles, uint64_t max_chunks,
+                               uint64_t max_buckets, uint64_t total_elems, SubDesc* subs, LeafDesc* leaves,
+                               unsigned long long* counters, uint64_t* dsz, uint32_t* err, hipStream_t stream);
+hipError_t launch_zero_words(uint32_t* p, uint32_t words, hipStream_t stream);
+hipError_t launch_check_one_level(const unsigned long long* counters, uint32_t* err, hipStream_t stream);
+
 // Sequential Fisher-Yates in global memory (recursion cap reached on a
 // subproblem that does not fit a tile).
 hipError_t launch_fy_global(uint32_t w, const LeafDesc* items, uint64_t count, hipStream_t stream);

@@ -478,3 +478,63 @@ def test_concurrent_host_threads_and_streams():
             shuf.shuffle_inplace_ex(t, 900 + i, i)
         torch.cuda.synchronize()
         assert np.array_equal(from_dev(tens[i], h), from_dev(t, h))
+
+
+def test_session_budget_queues_requests_and_matches_oracle():
+    """Admission by memory budget: with room for about two of the requests
+    (data plus the library's workspace for each), later requests wait in the
+    session's queue, the admitted charges never exceed the budget, a request
+    larger than the budget is refused, and every result equals the oracle."""
+    shuf = _lib()
+    w = 8
+    rng = np.random.default_rng(77)
+    sizes = [1 << 20, 3 << 19, 1 << 20, 700_001, 1 << 20, 50_000, 1, 0, 300_000]
+    reqs = []
+    for i, n in enumerate(sizes):
+        h = workloads.random_values(n, w, 500 + i)
+        reqs.append((h, int(rng.integers(0, 2**63)), i))
+    p = shuf.default_params(1 << 20, w)
+    charges = [h.shape[0] * w + (shuf.workspace_bytes(h.shape[0], w, sd, sid, p) if h.shape[0] > 1 else 0)
+               for h, sd, sid in reqs]
+    budget = 2 * max(charges) + 4096
+    print(f"[gpu] session budget {budget} charges {charges}", flush=True)
+    with shuf.Session(w) as sess:
+        sess.set_budget(budget)
+        big = torch.empty(budget // w + 1, dtype=torch.int64, device=_dev())
+        with pytest.raises(shuf.ShuffleError) as ei:
+            sess.submit(big, 1, 0)
+        assert ei.value.code == shuf.SHUF_ENOMEM
+        del big
+        tens = []
+        for h, sd, sid in reqs:
+            t = to_dev(h)
+            tens.append(t)
+            sess.submit(t, sd, sid)
+        saw_queue = False
+        steps = 0
+        while sess.inflight()[0]:
+            queued, used = sess.queued()
+            assert used <= budget
+            saw_queue = saw_queue or queued > 0
+            sess.step()
+            steps += 1
+            assert steps < 200
+        torch.cuda.synchronize()
+        assert saw_queue
+        assert sess.queued() == (0, 0)
+    for (h, sd, sid), t in zip(reqs, tens):
+        want = oracle_shuffle(h, sd, oracle.default_params(h.shape[0], w), stream_id=sid)
+        assert_same(from_dev(t, h), want, f"budgeted session request n={h.shape[0]}")
+
+
+@pytest.mark.parametrize("w", [4, 8, 16])
+def test_session_cheap_workspace_bound_covers_exact(w):
+    """The session's admission bound that needs no GPU work (n w + 24 n +
+    16 KiB of workspace) is at least the exact workspace of a request."""
+    shuf = _lib()
+    T = 65536 // w
+    for n in [T - 255, T + 1000, 5 * T + 17, 1 << 20, (3 << 21) + 5, (1 << 24) + 7]:
+        for sd, sid in [(1, 0), (2**64 - 1, 7)]:
+            exact = shuf.workspace_bytes(n, w, sd, sid)
+            print(f"[gpu] workspace n={n} w={w}: exact {exact} bound {n * w + 24 * n + 16384}", flush=True)
+            assert exact <= n * w + 24 * n + 16384, (n, w, exact)
