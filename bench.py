@@ -225,51 +225,56 @@ def batched_compare(torch, shuf, count: int = 10000, seed: int = 2026) -> dict:
 
     import workloads
 
+    from paper_2302_03317_amd import autotune
+
     sizes = workloads.log_uniform_sizes(count, 4, 20, seed=seed)
     offs = workloads.csr_offsets(sizes)
     host = workloads.batched_identity(sizes)
     total = int(host.size)
+    # the autotuner's parameters for this workload (every form below uses them)
+    found = autotune.lookup(autotune.load_table(), "batched_10000_u32", 4) if count == 10000 else None
+    p, table_version = found if found else (shuf.default_params(0, 4), None)
     a = torch.from_numpy(host.view(np.int32)).to("cuda:0")
     b = a.clone()
     views = [b[int(offs[j]):int(offs[j + 1])] for j in range(count)]
     s0 = int.from_bytes(os.urandom(8), "little")
-    shuf.shuffle_batched(a, offs, s0)          # warm-up (pools, first launches)
+    shuf.shuffle_batched(a, offs, s0, params=p)          # warm-up (pools, first launches)
     for j, v in enumerate(views):
         if v.shape[0] > 1:
-            shuf.shuffle_inplace_ex(v, s0, j)
+            shuf.shuffle_inplace_ex(v, s0, j, params=p)
     torch.cuda.synchronize()
     seed_t = int.from_bytes(os.urandom(8), "little")
     reps = 5
     t0 = time.perf_counter()
     for r in range(reps):
-        shuf.shuffle_batched(a, offs, seed_t + r)
+        shuf.shuffle_batched(a, offs, seed_t + r, params=p)
     torch.cuda.synchronize()
     t_batched = (time.perf_counter() - t0) / reps
     t0 = time.perf_counter()
     for r in range(reps):
         for j, v in enumerate(views):
             if v.shape[0] > 1:
-                shuf.shuffle_inplace_ex(v, seed_t + r, j)
+                shuf.shuffle_inplace_ex(v, seed_t + r, j, params=p)
     torch.cuda.synchronize()
     t_single = (time.perf_counter() - t0) / reps
     same = bool(torch.equal(a, b))
     # algorithmic bytes of one blocking batched call (every element each kernel
     # moves counted once read and once written), from the library's spans
     shuf.timing_enable(True)
-    shuf.shuffle_batched(a, offs, seed_t + 99)
+    shuf.shuffle_batched(a, offs, seed_t + 99, params=p)
     torch.cuda.synchronize()
     call_bytes = sum(v["bytes"] for v in shuf.timing_read().values())
     shuf.timing_enable(False)
     # the enqueue-only form: eager calls, and one call captured into a graph
     # and replayed (each replay shuffles the batch again with the captured seed)
-    wsb = shuf.batched_async_workspace_bytes(count, total, 4)
+    wsb = shuf.batched_async_workspace_bytes(count, total, 4, p)
     ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda:0")
     o = torch.tensor(np.asarray(offs, dtype=np.int64), device="cuda:0")
-    shuf.shuffle_batched_async(a, o, s0, ws, total)
+    shuf.shuffle_batched_async(a, o, s0, ws, total, params=p)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in range(reps):
-        shuf.shuffle_batched_async(a, o, seed_t + r, ws, total)
+        shuf.shuffle_batched_async(a, o, seed_t + r, ws, total, params=p)
     torch.cuda.synchronize()
     t_async = (time.perf_counter() - t0) / reps
     async_err = int(ws[:4].view(torch.int32).item())
@@ -278,7 +283,7 @@ def batched_compare(torch, shuf, count: int = 10000, seed: int = 2026) -> dict:
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.stream(gs):
         with torch.cuda.graph(graph, stream=gs):
-            shuf.shuffle_batched_async(a, o, seed_t + 1234, ws, total, stream=gs)
+            shuf.shuffle_batched_async(a, o, seed_t + 1234, ws, total, stream=gs, params=p)
     torch.cuda.synchronize()
     graph.replay()
     torch.cuda.synchronize()
@@ -301,12 +306,15 @@ def batched_compare(torch, shuf, count: int = 10000, seed: int = 2026) -> dict:
         "batched_algorithmic_bytes": call_bytes,
         "batched_GBs": call_bytes / t_batched / 1e9,
         "batched_frac_of_hbm_peak": call_bytes / t_batched / 1e9 / HBM_PEAK_GBS,
-        "form": "blocking: level by level in shared launches, default parameters, stream synchronised "
-                "after each tiled level (not graph-capturable)",
+        "params": {"tile": p.tile, "kmax_log2": p.kmax_log2, "n0": p.n0, "lmax": p.lmax},
+        "params_source": (f"autotuner table paper_2302_03317_amd/pi_table.json, version {table_version}"
+                          if table_version is not None else "defaults (no table entry)"),
+        "form": "blocking: level by level in shared launches, stream synchronised after each tiled "
+                "level (not graph-capturable)",
         "async_ms": t_async * 1e3,
         "async_Gelem_s": total / t_async / 1e9,
         "async_form": "enqueue-only: first level planned on the device, bounded grids, persistent "
-                      "leaf workgroups with per-class work counters, default parameters",
+                      "leaf workgroups with per-class work counters",
         "graph_replay_ms": t_graph * 1e3,
         "graph_replay_Gelem_s": total / t_graph / 1e9,
         "async_device_errors": [async_err, graph_err],

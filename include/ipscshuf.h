@@ -179,6 +179,15 @@ int shuffle_inplace_noalloc(void* ptr, uint64_t n, uint32_t elem_bytes, uint64_t
 int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
                     uint64_t seed, void* stream);
 
+/* shuffle_batched with explicit parameters for every array of the batch (an
+ * autotuned Π of the batched workload; Sec. 5 tunes k and the base-case size
+ * per workload by hand): array j is shuffled exactly as
+ * shuffle_inplace_ex(..., j, params).  params NULL means the defaults.
+ * Errors as shuffle_batched, plus SHUF_EINVAL / SHUF_EUNSUPPORTED for
+ * parameters that shuffle_inplace_ex refuses. */
+int shuffle_batched_ex(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
+                       uint64_t seed, const shuf_params_t* params, void* stream);
+
 /* Enqueue-only form of shuffle_batched (many independent shuffles run
  * together, Sec. 6.3): the call only launches kernels on `stream` -- no
  * host synchronisation, no allocation, no memset -- so a caller may capture it
@@ -188,21 +197,24 @@ int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t
  * the leaves run in persistent workgroups that take work from per-size-class
  * counters.  Array j is shuffled exactly as shuffle_inplace_ex(ptr +
  * offsets[j] * elem_bytes, offsets[j+1] - offsets[j], elem_bytes, seed, j,
- * default params), the same as shuffle_batched.
+ * params), the same as shuffle_batched_ex.
  *   offsets      DEVICE array of count + 1 non-decreasing element offsets,
  *                8-byte aligned, read when the kernels run
  *   count        1 .. 2^22 arrays
+ *   params       parameters of every array (NULL: the defaults); the same
+ *                pointer or equal values go to the two size queries below
  *   total_elems  an upper bound of offsets[count] (sizes the workspace)
  *   workspace    device memory of at least shuffle_batched_async_workspace_bytes
- *                (count, total_elems, elem_bytes) bytes, 256-byte aligned,
- *                owned by the caller and in use until the stream reaches the
- *                end of the call's work
- * Limit: every array holds at most shuffle_batched_async_max_elems(elem_bytes)
- * elements (one tiled level then leaves subproblems that fit a tile; 2^21 for
- * 4-byte elements).  Errors detected on the host (before any launch):
- * SHUF_EINVAL (NULL or misaligned pointers, bad width), SHUF_EUNSUPPORTED
- * (count or total_elems out of range), SHUF_ENOMEM (workspace too small),
- * SHUF_EHIP.  Errors detected on the device are reported in the first 4 bytes
+ *                (count, total_elems, elem_bytes, params) bytes, 256-byte
+ *                aligned, owned by the caller and in use until the stream
+ *                reaches the end of the call's work
+ * Limit: every array holds at most shuffle_batched_async_max_elems(elem_bytes,
+ * params) elements ((tile / 2) * 2^kmax_log2: one tiled level then leaves
+ * subproblems that fit a tile; 2^21 for 4-byte elements with the defaults;
+ * 0 for invalid parameters).  Errors detected on the host (before any
+ * launch): SHUF_EINVAL (NULL or misaligned pointers, bad width or
+ * parameters), SHUF_EUNSUPPORTED (count or total_elems out of range, or
+ * parameters beyond the LDS), SHUF_ENOMEM (workspace too small), SHUF_EHIP.  Errors detected on the device are reported in the first 4 bytes
  * of the workspace, to be read after the stream has completed: 0 success;
  * 32 decreasing offsets, an array above the limit or sizes beyond total_elems
  * (nothing was moved); 16 a subproblem needed a second tiled level (never
@@ -210,11 +222,11 @@ int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t
  * index check of the fix-up failed.  The device's first call of the library
  * runs a short probe that synchronises the stream: make it outside a capture. */
 int shuffle_batched_async(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
-                          uint64_t seed, uint64_t total_elems, void* workspace, uint64_t workspace_bytes,
-                          void* stream);
+                          uint64_t seed, const shuf_params_t* params, uint64_t total_elems, void* workspace,
+                          uint64_t workspace_bytes, void* stream);
 int shuffle_batched_async_workspace_bytes(uint64_t count, uint64_t total_elems, uint32_t elem_bytes,
-                                          uint64_t* out_bytes);
-uint64_t shuffle_batched_async_max_elems(uint32_t elem_bytes);
+                                          const shuf_params_t* params, uint64_t* out_bytes);
+uint64_t shuffle_batched_async_max_elems(uint32_t elem_bytes, const shuf_params_t* params);
 
 /* One array of a multi-array call or a serving request: n elements at device
  * pointer ptr (aligned to elem_bytes; may be NULL if n <= 1), shuffled with

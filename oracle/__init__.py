@@ -278,6 +278,26 @@ def position_histogram(n: int, seed0: int, nseeds: int, p: Params) -> np.ndarray
     return counts
 
 
+def params_from_table(path: str, workload: str, elem_bytes: int) -> tuple:
+    """(Params, table version) recorded for `workload` at this width in a
+    parameter table (JSON written by the library's autotuner).  The oracle
+    reads the file itself and takes only the four numbers of the entry; they
+    are inputs of the definition like a seed (the permutation is a function
+    of them), and check_params must accept them."""
+    import json
+
+    with open(path) as fh:
+        table = json.load(fh)
+    for e in table["entries"]:
+        if e["workload"] == workload and int(e["elem_bytes"]) == elem_bytes:
+            q = e["params"]
+            p = Params(tile=int(q["tile"]), kmax_log2=int(q["kmax_log2"]), n0=int(q["n0"]), lmax=int(q["lmax"]))
+            if not check_params(p):
+                raise ValueError(f"{path}: parameters of {workload} are outside the definition's ranges")
+            return p, int(table["version"])
+    raise KeyError(f"{path} has no entry for {workload} at {elem_bytes} bytes")
+
+
 def default_params(n: int, elem_bytes: int) -> Params:
     """The default parameters for (n, elem_bytes): a 64 KiB tile."""
     tile_bytes = 65536

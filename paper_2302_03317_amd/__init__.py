@@ -107,6 +107,8 @@ def lib() -> ctypes.CDLL:
         L.shuffle_inplace_ex.restype = i
         L.shuffle_batched.argtypes = [vp, ctypes.POINTER(u64), u64, u32, u64, vp]
         L.shuffle_batched.restype = i
+        L.shuffle_batched_ex.argtypes = [vp, ctypes.POINTER(u64), u64, u32, u64, ctypes.POINTER(_Params), vp]
+        L.shuffle_batched_ex.restype = i
         L.shuffle_workspace_bytes.argtypes = [u64, u32, u64, u32, ctypes.POINTER(_Params),
                                               ctypes.POINTER(u64), vp]
         L.shuffle_workspace_bytes.restype = i
@@ -138,11 +140,12 @@ def lib() -> ctypes.CDLL:
         L.shuffle_timing_read.restype = i
         L.shuffle_inplace_noalloc.argtypes = [vp, u64, u32, u64, u32, ctypes.POINTER(_Params), vp]
         L.shuffle_inplace_noalloc.restype = i
-        L.shuffle_batched_async.argtypes = [vp, vp, u64, u32, u64, u64, vp, u64, vp]
+        L.shuffle_batched_async.argtypes = [vp, vp, u64, u32, u64, ctypes.POINTER(_Params), u64, vp, u64, vp]
         L.shuffle_batched_async.restype = i
-        L.shuffle_batched_async_workspace_bytes.argtypes = [u64, u64, u32, ctypes.POINTER(u64)]
+        L.shuffle_batched_async_workspace_bytes.argtypes = [u64, u64, u32, ctypes.POINTER(_Params),
+                                                            ctypes.POINTER(u64)]
         L.shuffle_batched_async_workspace_bytes.restype = i
-        L.shuffle_batched_async_max_elems.argtypes = [u32]
+        L.shuffle_batched_async_max_elems.argtypes = [u32, ctypes.POINTER(_Params)]
         L.shuffle_batched_async_max_elems.restype = u64
         L.shuffle_release.argtypes = []
         L.shuffle_release.restype = i
@@ -259,32 +262,42 @@ def shuffle_inplace_ws(tensor, seed: int, workspace, stream_id: int = 0,
         raise ShuffleError(rc, "shuffle_inplace_ws")
 
 
-def batched_async_workspace_bytes(count: int, total_elems: int, elem_bytes: int) -> int:
+def _cparams_or_null(params: Params | None):
+    if params is None:
+        return None
+    return ctypes.byref(_Params(params.tile, params.kmax_log2, params.n0, params.lmax))
+
+
+def batched_async_workspace_bytes(count: int, total_elems: int, elem_bytes: int,
+                                  params: Params | None = None) -> int:
     out = ctypes.c_uint64()
-    rc = lib().shuffle_batched_async_workspace_bytes(count, total_elems, elem_bytes, ctypes.byref(out))
+    rc = lib().shuffle_batched_async_workspace_bytes(count, total_elems, elem_bytes, _cparams_or_null(params),
+                                                     ctypes.byref(out))
     if rc != SHUF_OK:
         raise ShuffleError(rc, "shuffle_batched_async_workspace_bytes")
     return int(out.value)
 
 
-def batched_async_max_elems(elem_bytes: int) -> int:
-    return int(lib().shuffle_batched_async_max_elems(elem_bytes))
+def batched_async_max_elems(elem_bytes: int, params: Params | None = None) -> int:
+    return int(lib().shuffle_batched_async_max_elems(elem_bytes, _cparams_or_null(params)))
 
 
 def shuffle_batched_async(tensor, offsets, seed: int, workspace, total_elems: int | None = None,
-                          stream=None) -> None:
+                          stream=None, params: Params | None = None) -> None:
     """Enqueue the batched shuffle of `tensor` (rows [offsets[j], offsets[j+1])
     form array j) on the stream without synchronising: `offsets` is a device
     int64 tensor of count + 1 entries, `workspace` a device tensor of at least
-    batched_async_workspace_bytes(...) bytes whose first int32 reads 0 after
-    the stream has completed if the device found no error."""
+    batched_async_workspace_bytes(..., params) bytes whose first int32 reads 0
+    after the stream has completed if the device found no error.  `params`
+    (default: the defaults) apply to every array."""
     n, w = _geometry(tensor)
     count = offsets.numel() - 1
     total = n if total_elems is None else int(total_elems)
     wb = workspace.numel() * workspace.element_size()
     rc = lib().shuffle_batched_async(
         ctypes.c_void_p(tensor.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), count, w, seed & (2**64 - 1),
-        total, ctypes.c_void_p(workspace.data_ptr()), wb, _stream_handle(tensor, stream),
+        _cparams_or_null(params), total, ctypes.c_void_p(workspace.data_ptr()), wb,
+        _stream_handle(tensor, stream),
     )
     if rc != SHUF_OK:
         raise ShuffleError(rc, "shuffle_batched_async")
@@ -305,17 +318,18 @@ def shuffle_inplace_noalloc(tensor, seed: int, stream_id: int = 0, params: Param
         raise ShuffleError(rc, "shuffle_inplace_noalloc")
 
 
-def shuffle_batched(tensor, offsets, seed: int, stream=None) -> None:
+def shuffle_batched(tensor, offsets, seed: int, stream=None, params: Params | None = None) -> None:
     """Shuffle the arrays packed in `tensor` (rows [offsets[j], offsets[j+1])
-    form array j) in place, each with stream id j and default parameters."""
+    form array j) in place, each with stream id j and `params` (default: the
+    defaults)."""
     n, w = _geometry(tensor)
     offs = [int(o) for o in offsets]
     if len(offs) < 1 or offs[-1] > n:
         raise ValueError("offsets must end within the tensor")
     arr = (ctypes.c_uint64 * len(offs))(*offs)
-    rc = lib().shuffle_batched(
+    rc = lib().shuffle_batched_ex(
         ctypes.c_void_p(tensor.data_ptr()), arr, len(offs) - 1, w, seed & (2**64 - 1),
-        _stream_handle(tensor, stream),
+        _cparams_or_null(params), _stream_handle(tensor, stream),
     )
     if rc != SHUF_OK:
         raise ShuffleError(rc, "shuffle_batched")

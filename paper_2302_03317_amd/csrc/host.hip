@@ -976,6 +976,24 @@ AsyncLayout async_layout(uint64_t count, uint64_t total_elems, uint32_t w, const
 int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
                     uint64_t seed, void* stream)
 {
+    return shuffle_batched_ex(ptr, offsets, count, elem_bytes, seed, nullptr, stream);
+}
+
+// Parameters of a batched call: the caller's, or the defaults for the width.
+static int batched_params(const shuf_params_t* params, uint32_t w, shuf_params_t* out)
+{
+    if (params) {
+        *out = *params;
+    } else {
+        const int rc = shuf_default_params(0, w, out);
+        if (rc != SHUF_OK) return rc;
+    }
+    return check_params(out, w);
+}
+
+int shuffle_batched_ex(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
+                       uint64_t seed, const shuf_params_t* params, void* stream)
+{
     if (!valid_width(elem_bytes) || !offsets) return SHUF_EINVAL;
     if (count >= (1ull << 32)) return SHUF_EUNSUPPORTED;
     bool any = false;
@@ -989,8 +1007,7 @@ int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t
     if (!ptr) return SHUF_EINVAL;
     if (reinterpret_cast<uintptr_t>(ptr) % elem_bytes) return SHUF_EINVAL;
     shuf_params_t p;
-    shuf_default_params(0, elem_bytes, &p);
-    int rc = check_params(&p, elem_bytes);
+    int rc = batched_params(params, elem_bytes, &p);
     if (rc != SHUF_OK) return rc;
     Engine E = make_engine(elem_bytes, p);
     const uint64_t base = reinterpret_cast<uintptr_t>(ptr) / elem_bytes;
@@ -1002,39 +1019,39 @@ int shuffle_batched(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t
 }
 
 int shuffle_batched_async_workspace_bytes(uint64_t count, uint64_t total_elems, uint32_t elem_bytes,
-                                          uint64_t* out_bytes)
+                                          const shuf_params_t* params, uint64_t* out_bytes)
 {
     if (!out_bytes || !valid_width(elem_bytes)) return SHUF_EINVAL;
-    if (count == 0 || count > kAsyncMaxCount || total_elems >= kMaxElements) return SHUF_EUNSUPPORTED;
     shuf_params_t p;
-    shuf_default_params(0, elem_bytes, &p);
+    const int rc = batched_params(params, elem_bytes, &p);
+    if (rc != SHUF_OK) return rc;
+    if (count == 0 || count > kAsyncMaxCount || total_elems >= kMaxElements) return SHUF_EUNSUPPORTED;
     *out_bytes = async_layout(count, total_elems, elem_bytes, Params{p.tile, p.kmax_log2, p.n0, p.lmax, 0}).total;
     return SHUF_OK;
 }
 
-uint64_t shuffle_batched_async_max_elems(uint32_t elem_bytes)
+uint64_t shuffle_batched_async_max_elems(uint32_t elem_bytes, const shuf_params_t* params)
 {
     if (!valid_width(elem_bytes)) return 0;
     shuf_params_t p;
-    shuf_default_params(0, elem_bytes, &p);
+    if (batched_params(params, elem_bytes, &p) != SHUF_OK) return 0;
     // one tiled level leaves subproblems that fit a tile: kappa covers every
     // label bit the size needs when (T / 2) * 2^KMAXLOG2 >= n
     return static_cast<uint64_t>(p.tile / 2) << p.kmax_log2;
 }
 
 int shuffle_batched_async(void* ptr, const uint64_t* offsets, uint64_t count, uint32_t elem_bytes,
-                          uint64_t seed, uint64_t total_elems, void* workspace, uint64_t workspace_bytes,
-                          void* stream)
+                          uint64_t seed, const shuf_params_t* params, uint64_t total_elems, void* workspace,
+                          uint64_t workspace_bytes, void* stream)
 {
     if (!valid_width(elem_bytes) || !offsets || !workspace) return SHUF_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace) % 256 || reinterpret_cast<uintptr_t>(offsets) % 8)
         return SHUF_EINVAL;
-    if (count == 0 || count > kAsyncMaxCount || total_elems >= kMaxElements) return SHUF_EUNSUPPORTED;
     if (!ptr || reinterpret_cast<uintptr_t>(ptr) % elem_bytes) return SHUF_EINVAL;
     shuf_params_t sp;
-    shuf_default_params(0, elem_bytes, &sp);
-    int rc = check_params(&sp, elem_bytes);
+    int rc = batched_params(params, elem_bytes, &sp);
     if (rc != SHUF_OK) return rc;
+    if (count == 0 || count > kAsyncMaxCount || total_elems >= kMaxElements) return SHUF_EUNSUPPORTED;
     Params prm{sp.tile, sp.kmax_log2, sp.n0, sp.lmax, 0};
     const AsyncLayout L = async_layout(count, total_elems, elem_bytes, prm);
     if (workspace_bytes < L.total) return SHUF_ENOMEM;
@@ -1065,7 +1082,7 @@ int shuffle_batched_async(void* ptr, const uint64_t* offsets, uint64_t count, ui
     uint64_t* total = reinterpret_cast<uint64_t*>(W + L.header + 136);
     const uint64_t kmax = 1ull << prm.kmax_log2;
     const uint64_t tile_limit = prm.tile - kmax;
-    const uint64_t max_elems = std::min<uint64_t>(shuffle_batched_async_max_elems(elem_bytes), total_elems);
+    const uint64_t max_elems = std::min<uint64_t>(shuffle_batched_async_max_elems(elem_bytes, &sp), total_elems);
 
     HIP_TRY(launch_zero_words(err, static_cast<uint32_t>(kAsyncHeaderBytes / 4), st));
     SubDesc* subs = reinterpret_cast<SubDesc*>(W + L.subs);

@@ -134,6 +134,53 @@ def test_async_repeated_calls_equal_oracle():
         assert not bad, f"run {run}: arrays {bad[:10]} differ from the oracle"
 
 
+def test_tuned_params_batched_equals_oracle():
+    """The 10,000-array workload with the parameters of the autotuner's table,
+    read by the library's reader for the GPU call and by the oracle's own
+    reader for the expected result (arrays solved on host threads)."""
+    import hashlib
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2302_03317_amd import autotune
+
+    shuf = _lib()
+    table_path = os.path.join(os.path.dirname(HERE), "paper_2302_03317_amd", "pi_table.json")
+    p_lib, version = autotune.lookup(autotune.load_table(table_path), "batched_10000_u32", 4)
+    p_or, _ = oracle.params_from_table(table_path, "batched_10000_u32", 4)
+    sizes = workloads.log_uniform_sizes(10000, 4, 20, seed=2026)
+    offs = workloads.csr_offsets(sizes)
+    host = workloads.batched_identity(sizes)
+    seed = 0x2302033172026005
+    print(f"[gpu] tuned parameters (table version {version}): {p_lib}, arrays={len(sizes)} total={host.size}",
+          flush=True)
+    t = to_dev(host)
+    dev = _dev()
+    total = int(offs[-1])
+    wsb = shuf.batched_async_workspace_bytes(len(sizes), total, 4, p_lib)
+    ws = torch.zeros(wsb, dtype=torch.uint8, device=dev)
+    o = torch.tensor(np.asarray(offs, dtype=np.int64), device=dev)
+    shuf.shuffle_batched_async(t, o, seed, ws, total, params=p_lib)
+    torch.cuda.synchronize()
+    assert int(ws[:4].view(torch.int32).item()) == 0
+    got = hashlib.sha256(t.cpu().numpy().view(np.uint8)).hexdigest()
+    b = to_dev(host)
+    shuf.shuffle_batched(b, offs, seed, params=p_lib)
+    torch.cuda.synchronize()
+    assert torch.equal(b, t), "blocking and enqueue-only forms differ with the tuned parameters"
+    del t, b, ws
+
+    want = host.copy()
+
+    def one(j):
+        a, e = int(offs[j]), int(offs[j + 1])
+        if e - a > 1:
+            oracle.shuffle(want[a:e], seed, p_or, stream_id=j)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(one, range(len(sizes))))
+    assert got == hashlib.sha256(want.view(np.uint8)).hexdigest()
+
+
 def test_async_captured_graph_replays():
     """Captured once into a HIP graph and replayed three times, with other
     work and synchronisations between the replays: replay r leaves the
