@@ -241,6 +241,23 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Start copying words [j0, nw) of a run, in chunks of 256 words from j0 on
+// with a stride of `stride` words (a multiple of 256), from global memory
+// straight into LDS (direct global-to-LDS loads: the data land in LDS
+// without passing through registers).  Called by a whole wave.  Lane l
+// moves words 4l .. 4l + 3 of a chunk with one 16-byte load; the at most
+// three words past the last multiple of four move with 4-byte loads by the
+// wave that starts at j0 = 0.  Addresses need only be 4-byte aligned.  The
+// caller waits (vmcnt) and synchronises before reading the LDS copy.
+__device__ __forceinline__ void copy_run_to_lds(const global_t<uint32_t>* src, uint32_t* dst, uint32_t nw,
+                                                uint32_t j0, uint32_t stride, uint32_t lane)
+{
+    const uint32_t nv = nw & ~3u;
+    for (uint32_t j = j0; j < nv; j += stride)
+        if (j + 4u * lane < nv) __builtin_amdgcn_global_load_lds(src + j + 4u * lane, dst + j, 16, 0, 0);
+    if (j0 == 0 && lane < nw - nv) __builtin_amdgcn_global_load_lds(src + nv + lane, dst + nv, 4, 0, 0);
+}
+
 // The workgroup barrier of every kernel here: this wave's LDS operations are
 // complete before it (an explicit lgkmcnt(0) wait), so every LDS write made
 // before the barrier is seen by every wave after it.  The wait is not left to

@@ -50,7 +50,9 @@ __device__ __forceinline__ uint32_t kappa_in_tile(uint32_t m, const Params& prm)
 // a wave run different segments, so each lane starts after o idle steps, o
 // chosen so that every lane enters a new block on the same step: the block
 // is then computed once per eight steps for the whole wave, and the 16-bit
-// word a step uses is known at compile time.
+// word a step uses is known at compile time.  (Batching steps into one LDS
+// round trip with the swaps resolved in registers measured slower: the
+// chains of different lanes and waves already overlap.)
 __device__ __forceinline__ void fy_segment(uint16_t* idx, uint32_t s0, uint32_t len, uint64_t pbase,
                                            uint32_t level, const Key& key)
 {
@@ -398,9 +400,7 @@ __device__ __forceinline__ void leaf_body(const LeafDesc ld, const Params& prm, 
         const uint32_t nw = m * static_cast<uint32_t>(sizeof(E) / 4);
         const global_t<uint32_t>* from = reinterpret_cast<const global_t<uint32_t>*>(X);
         uint32_t* to = reinterpret_cast<uint32_t*>(stage);
-        for (uint32_t j = wv * 64u; j < nw; j += kThreads) {
-            if (j + lane < nw) __builtin_amdgcn_global_load_lds(from + j + lane, to + j, 4, 0, 0);
-        }
+        copy_run_to_lds(from, to, nw, wv * 256u, kWaves * 256u, lane);
         __builtin_amdgcn_s_waitcnt(0);
     }
     block_sync();
