@@ -50,9 +50,9 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {
     ("u32_2e32", "rough"): {
         "read_bytes": 20.233e9,
-        "write_bytes": 20.658e9,
+        "write_bytes": 20.659e9,
         "sources": ["k_rough.hip", "common.hpp", "rng.hpp", "kernels.hpp"],
-        "sha256": "c919cc8e3995e44213162f2fd4bd9694de1b7d055f43218cf8c5db1bcccd1b04",
+        "sha256": "aada210dcbaa6174933540e176d5ae6745793aa0ddd42ef036c02b5c5fda09fb",
     },
 }
 
