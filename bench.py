@@ -567,6 +567,10 @@ def main() -> int:
         "levels": {"tiled_levels": stats["tiled_levels"], "movers_last_step": stats["movers"],
                    "leaves_last_step": stats["leaves"], "workspace_bytes": stats["workspace_bytes"]},
         "checksum_preserved": before == after,
+        # how the kernels took the stable ranks on this device (both ways give
+        # the same permutation): 1 = LDS atomic adds, whose lane order the
+        # device's probe checked at the first call; 0 = ballots
+        "rank_method": {1: "lds_atomic_lane_order_probed", 0: "ballot"}.get(shuf.rank_method(), "none"),
     }
     if not args.no_batched:
         del t

@@ -52,16 +52,21 @@ def test_ballot_ranks_match_oracle_in_own_process():
 
 
 def test_many_small_random_cases_match_oracle():
-    """Many small random cases (sizes, widths, parameters, seeds) against the
-    oracle: the ranks of every in-tile and tiled level, whichever way the
-    device computes them, must keep the oracle's permutation."""
+    """120 small random cases (sizes, widths, parameters, seeds) that the
+    library accepts, against the oracle: the ranks of every in-tile and tiled
+    level, whichever way the device computes them, must keep the oracle's
+    permutation.  Parameter sets whose LDS layout exceeds a CU are refused
+    before any work (counted and printed) and replaced by further draws."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2302_03317_amd as shuf
 
     rng = np.random.default_rng(2302)
     unsupported = 0
-    for case in range(120):
+    ran = 0
+    for case in range(400):
+        if ran == 120:
+            break
         w = int(rng.choice([4, 8, 16]))
         n = int(rng.integers(2, 30000))
         kmax_log2 = int(rng.integers(1, 9))
@@ -87,4 +92,7 @@ def test_many_small_random_cases_match_oracle():
         want = host.copy()
         oracle.shuffle(want, seed, p, stream_id=case)
         assert np.array_equal(got, want), f"case {case}"
-    assert unsupported < 30, unsupported
+        ran += 1
+    print(f"[gpu] {ran} random cases matched the oracle; {unsupported} parameter sets refused "
+          f"(LDS layout beyond one CU) before any work", flush=True)
+    assert ran == 120, (ran, unsupported)
