@@ -513,14 +513,15 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     HIP_TRY(mem.take(C.err, 4, &p_err));
     HIP_TRY(H.err.ensure(4));
     HIP_TRY(hipMemsetAsync(p_err, 0, 4, stream));
-    HIP_TRY(mem.take(C.counters, 48, &p_counters));
+    HIP_TRY(mem.take(C.counters, 72, &p_counters));
     HIP_TRY(H.counters.ensure(48));
     HIP_TRY(mem.take(C.total, 8, &p_total));
     HIP_TRY(H.total.ensure(8));
     unsigned long long* dc = static_cast<unsigned long long*>(p_counters);
     unsigned long long* hc = H.counters.as<unsigned long long>();
-    // [0] leaf children, [1] big children, [2] leaf child elements, [3..5] leaves per class
-    HIP_TRY(hipMemsetAsync(dc, 0, 48, stream));
+    // [0] leaf children, [1] big children, [2] leaf child elements, [3..5] leaves per class,
+    // [6..8] the leaf classes' work counters
+    HIP_TRY(hipMemsetAsync(dc, 0, 72, stream));
 
     std::vector<uint8_t> had_tiled(E.ticket.size(), 0);
 
@@ -710,8 +711,8 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
     }
     if (run_leaves && !dry) {
         SpanGuard g(C, stream, 4, 2.0 * static_cast<double>(run_leaf_elems) * w);
-        HIP_TRY(launch_leaf(w, static_cast<const LeafDesc*>(p_cls), count, run_leaves, prm, caps,
-                            stream));
+        HIP_TRY(launch_leaf_persistent(w, static_cast<const LeafDesc*>(p_cls), dc + 3, run_leaves, prm, caps,
+                                       dc + 6, stream));
     }
     if (!gfy.empty()) {
         void* p_gfy;
