@@ -2,8 +2,9 @@
 // levels of ScatterShuffle (arXiv 2302.03317, Sec. 3.1 / Fig. 2) and the
 // Fisher-Yates base case (Fig. 1).
 //
-// One workgroup per subproblem ("leaf").  Only 16-bit indices move while the
-// levels run: idx[x] is the original
+// One workgroup at a time per subproblem ("leaf"); persistent workgroups take
+// the leaves of a size class one after another.  Only 16-bit indices move
+// while the levels run: idx[x] is the original
 // leaf index of the item at position x.  Each in-tile level is a stable
 // counting sort of every splitting segment by its label; segments larger
 // than one wave can hold are split by the whole workgroup, the others by one
@@ -411,17 +412,9 @@ __device__ __forceinline__ void leaf_body(const LeafDesc ld, const Params& prm, 
     }
 }
 
-// One size class of leaves, one workgroup per leaf, MINW waves per SIMD.
-template <typename E, int ROUNDS, int MINW>
-__global__ __launch_bounds__(kThreads, MINW) void k_leaf(const LeafDesc* __restrict__ leaves,
-                                                         Params prm, uint32_t cap)
-{
-    extern __shared__ __align__(16) uint8_t smem[];
-    leaf_body<E, ROUNDS>(leaves[xcd_order(blockIdx.x, gridDim.x)], prm, cap, smem);
-}
-
-// The same with persistent workgroups: each takes the next leaf of the class
-// from the work counter *qctr until *count leaves are taken.
+// One size class of leaves, MINW waves per SIMD, in persistent workgroups:
+// each takes the next leaf of the class from the work counter *qctr until
+// *count leaves are taken.
 template <typename E, int ROUNDS, int MINW>
 __global__ __launch_bounds__(kThreads, MINW) void k_leaf_persistent(const LeafDesc* __restrict__ leaves,
                                                                     const unsigned long long* __restrict__ count,
@@ -474,31 +467,6 @@ struct LeafClasses {
     static constexpr int kRoundsM = static_cast<int>((kTmax / 2 + kTmax / 32 + kThreads - 1) / kThreads);
     static constexpr int kRoundsS = static_cast<int>((kTmax / 4 + kTmax / 32 + kThreads - 1) / kThreads);
 };
-
-template <typename E, int ROUNDS, int MINW>
-hipError_t leaf_class_t(const LeafDesc* leaves, uint64_t n, const Params& prm, uint32_t cap,
-                        hipStream_t stream)
-{
-    if (n == 0) return hipSuccess;
-    if (cap > static_cast<uint32_t>(ROUNDS) * kThreads) return hipErrorInvalidValue;
-    const LeafLayout LL = leaf_layout(cap, sizeof(E), 1u << prm.kmax_log2, prm.n0);
-    hipLaunchKernelGGL((k_leaf<E, ROUNDS, MINW>), dim3(static_cast<uint32_t>(n)), dim3(kThreads),
-                       LL.total, stream, leaves, prm, cap);
-    return hipGetLastError();
-}
-
-template <typename E>
-hipError_t leaf_t(const LeafDesc* leaves, const uint64_t* count, uint64_t stride, const Params& prm,
-                  const uint32_t* caps, hipStream_t stream)
-{
-    using LC = LeafClasses<E>;
-    hipError_t e;
-    e = leaf_class_t<E, LC::kRoundsS, 8>(leaves, count[0], prm, caps[0], stream);
-    if (e != hipSuccess) return e;
-    e = leaf_class_t<E, LC::kRoundsM, 6>(leaves + stride, count[1], prm, caps[1], stream);
-    if (e != hipSuccess) return e;
-    return leaf_class_t<E, LC::kRoundsL, 4>(leaves + 2 * stride, count[2], prm, caps[2], stream);
-}
 
 template <typename E, int ROUNDS, int MINW>
 hipError_t leaf_class_persistent_t(const LeafDesc* leaves, const unsigned long long* count,
@@ -632,17 +600,6 @@ hipError_t launch_leaf_persistent(uint32_t w, const LeafDesc* leaves, const unsi
     }
 }
 
-hipError_t launch_leaf(uint32_t w, const LeafDesc* leaves, const uint64_t* count, uint64_t stride,
-                       const Params& prm, const uint32_t* caps, hipStream_t stream)
-{
-    switch (w) {
-    case 4: return leaf_t<uint32_t>(leaves, count, stride, prm, caps, stream);
-    case 8: return leaf_t<uint64_t>(leaves, count, stride, prm, caps, stream);
-    case 16: return leaf_t<Elem16>(leaves, count, stride, prm, caps, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
-
 template <typename E>
 static hipError_t leaf_limits_t()
 {
@@ -654,17 +611,8 @@ static hipError_t leaf_limits_t()
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsM, 6>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax - 64);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsL, 4>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax - 64);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<E, LC::kRoundsS, 8>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<E, LC::kRoundsM, 6>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf<E, LC::kRoundsL, 4>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsL, 4>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax - 64);
 }
 
 hipError_t set_leaf_lds_limits()

@@ -90,12 +90,10 @@ void leaf_class_caps(uint32_t w, const Params& prm, uint32_t* caps);
 hipError_t launch_leaf_classes(const LeafDesc* in, uint64_t n, LeafDesc* out, uint64_t stride,
                                const uint32_t* caps, unsigned long long* count, hipStream_t stream,
                                const unsigned long long* dn = nullptr);
-// leaves of class c are leaves[c * stride, c * stride + count[c])
-hipError_t launch_leaf(uint32_t w, const LeafDesc* leaves, const uint64_t* count, uint64_t stride,
-                       const Params& prm, const uint32_t* caps, hipStream_t stream);
-// The same with the class counts in device memory (dcount[0..2]): persistent
-// workgroups, as many as the device holds at once, take leaves from the
-// per-class work counters qctr[0..2] (zero on entry) until none are left.
+// The leaves of class c are leaves[c * stride, c * stride + dcount[c]), the
+// counts in device memory: persistent workgroups, as many as the device holds
+// at once, take leaves from the per-class work counters qctr[0..2] (zero on
+// entry) until none are left.
 hipError_t launch_leaf_persistent(uint32_t w, const LeafDesc* leaves, const unsigned long long* dcount,
                                   uint64_t stride, const Params& prm, const uint32_t* caps,
                                   unsigned long long* qctr, hipStream_t stream);
