@@ -52,7 +52,7 @@ TRAFFIC = {
         "read_bytes": 20.233e9,
         "write_bytes": 20.659e9,
         "sources": ["k_rough.hip", "common.hpp", "rng.hpp", "kernels.hpp"],
-        "sha256": "aada210dcbaa6174933540e176d5ae6745793aa0ddd42ef036c02b5c5fda09fb",
+        "sha256": "46497409a850e8a83b178b672cf655afa46e8b4dade9cce7d8f77f639ca913c6",
     },
 }
 
