@@ -422,14 +422,18 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf_persistent(const LeafDe
                                                                     Params prm, uint32_t cap)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ unsigned long long take;
+    // take[it & 1] holds the leaf of iteration it; thread 0 takes the next
+    // leaf while the current one runs, so the atomic's latency is hidden.
+    // Slot (it + 1) & 1 is written after every thread read it in iteration
+    // it - 1 and read after the barriers that end iteration it.
+    __shared__ unsigned long long take[2];
     const unsigned long long total = *count;
-    for (;;) {
-        if (threadIdx.x == 0) take = atomicAdd(qctr, 1ull);
-        block_sync();
-        const unsigned long long i = take;
-        block_sync();  // every thread has read it before the next take
+    if (threadIdx.x == 0) take[0] = atomicAdd(qctr, 1ull);
+    block_sync();
+    for (uint32_t it = 0;; ++it) {
+        const unsigned long long i = take[it & 1u];
         if (i >= total) break;
+        if (threadIdx.x == 0) take[(it + 1) & 1u] = atomicAdd(qctr, 1ull);
         leaf_body<E, ROUNDS>(leaves[i], prm, cap, smem);
         block_sync();  // the next leaf reuses the LDS
     }
