@@ -76,6 +76,49 @@ def test_async_ragged_batch_equals_oracle(w):
         assert np.array_equal(got[a:b], want), f"async w={w} array {j} (n={s})"
 
 
+@pytest.mark.parametrize("tile_bytes,kmax_log2,n0", [(32768, 8, 32), (65536, 7, 128), (65536, 6, 16),
+                                                    (16384, 8, 48)])
+def test_async_nondefault_params_equal_oracle(tile_bytes, kmax_log2, n0):
+    """The enqueue-only call with parameters other than the defaults (the
+    autotuner's candidates and smaller tiles), u32 and u64 arrays up to the
+    largest size those parameters finish in one tiled level, against the
+    oracle with the same parameters; the blocking batched call with the same
+    parameters must give the same bytes."""
+    shuf = _lib()
+    for w in (4, 8):
+        p = shuf.Params(tile_bytes // w, kmax_log2, n0, 32)
+        mx = shuf.batched_async_max_elems(w, p)
+        assert mx == (p.tile // 2) << kmax_log2
+        T = p.tile
+        sizes = [mx, 0, 2, T - (1 << kmax_log2), T - (1 << kmax_log2) + 1, 3 * T + 5, 77, mx - 3, 1, 5000]
+        parts = [workloads.random_values(sz, w, 7000 + i) for i, sz in enumerate(sizes)]
+        host = np.concatenate(parts, axis=0)
+        offs = workloads.csr_offsets(np.array(sizes, dtype=np.uint64))
+        print(f"[gpu] async params tile={p.tile} kmax_log2={kmax_log2} n0={n0} w={w} total={host.shape[0]}",
+              flush=True)
+        dev = _dev()
+        t = to_dev(host)
+        total = int(offs[-1])
+        wsb = shuf.batched_async_workspace_bytes(len(sizes), total, w, p)
+        ws = torch.zeros(wsb, dtype=torch.uint8, device=dev)
+        o = torch.tensor(np.asarray(offs, dtype=np.int64), device=dev)
+        shuf.shuffle_batched_async(t, o, 31337, ws, total, params=p)
+        torch.cuda.synchronize()
+        assert int(ws[:4].view(torch.int32).item()) == 0
+        b = to_dev(host)
+        shuf.shuffle_batched(b, offs, 31337, params=p)
+        torch.cuda.synchronize()
+        assert torch.equal(t, b)
+        got = from_dev(t, host)
+        op = oracle.Params(p.tile, p.kmax_log2, p.n0, p.lmax)
+        for j, sz in enumerate(sizes):
+            a, e = int(offs[j]), int(offs[j + 1])
+            want = host[a:e].copy()
+            if sz > 1:
+                oracle.shuffle(want, 31337, op, stream_id=j)
+            assert np.array_equal(got[a:e], want), f"array {j} (n={sz})"
+
+
 def test_async_equals_blocking_batched_on_random_sizes():
     shuf = _lib()
     sizes = workloads.log_uniform_sizes(700, 0, 20, seed=17)
