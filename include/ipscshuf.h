@@ -25,7 +25,8 @@
  *     data_ptr()); the library never frees it;
  *   - `stream` is a hipStream_t (NULL = the null stream).  The work runs on
  *     that stream; the call returns after it has completed (the library
- *     synchronises the stream to plan each recursion level);
+ *     synchronises the stream to plan each recursion level), except
+ *     shuffle_batched_async, which only enqueues its work;
  *   - device memory is addressed absolutely: every array, wherever it lives,
  *     is reached through its own pointer;
  *   - argument errors are detected before any GPU work starts, and then the
