@@ -21,6 +21,9 @@ namespace ipss {
 namespace {
 
 constexpr int kTabThreads = 256;
+// Threads of a gather or scatter workgroup (one tile each); 128, 512 and
+// 1024 measured slower.
+constexpr int kFixThreads = 256;
 // Subproblems of more chunks than this get one wave per bucket in the
 // per-bucket reductions over chunks.
 constexpr uint64_t kWaveChunks = 16;
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(kChildThreads) void k_children(LevelTables T, uint3
 
 // ---- gather: movers of one tile into the workspace ----
 template <typename E>
-__global__ __launch_bounds__(kTabThreads) void k_gather(E* __restrict__ ws, LevelTables T)
+__global__ __launch_bounds__(kFixThreads) void k_gather(E* __restrict__ ws, LevelTables T)
 {
     __shared__ uint64_t lo[kKmax], kept_lo[kKmax], base_w[kKmax];
     __shared__ uint32_t fill[kKmax], kept[kKmax], disp[kKmax];
@@ -476,7 +479,7 @@ __global__ __launch_bounds__(kTabThreads) void k_gather(E* __restrict__ ws, Leve
     const uint32_t k = 1u << sd.kappa;
     const global_t<E>* X = elem_gptr<E>(sd.elem_off) + sd.base;
     const TilePieces tp(sd.m, sd.kappa, sd.tiles, t, T.tile_pofs + 2 * g);
-    for (uint32_t b = tid; b < k; b += kTabThreads) {
+    for (uint32_t b = tid; b < k; b += kFixThreads) {
         const uint64_t e = sd.tab_off + t * k + b;
         const uint64_t gb = sd.bk_off + b;
         const Stats st = piece_stats(tp.of(b), T.cnt[e], T.S[gb], T.N[gb]);
@@ -496,7 +499,7 @@ __global__ __launch_bounds__(kTabThreads) void k_gather(E* __restrict__ ws, Leve
     if (wv == 2) wave_exclusive_scan(outt, k);
     block_sync();
     const uint32_t nout = outt[k];
-    for (uint32_t i = tid; i < nout; i += kTabThreads) {
+    for (uint32_t i = tid; i < nout; i += kFixThreads) {
         const uint32_t b = upper_index(outt, k, i);
         const uint32_t j = i - outt[b];
         uint64_t pos;
@@ -522,7 +525,7 @@ __global__ __launch_bounds__(kTabThreads) void k_gather(E* __restrict__ ws, Leve
 
 // ---- scatter: free slots of the tile's pieces from the workspace ----
 template <typename E>
-__global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ ws, LevelTables T)
+__global__ __launch_bounds__(kFixThreads) void k_scatter(const E* __restrict__ ws, LevelTables T)
 {
     __shared__ uint64_t S[kKmax], Ktot[kKmax], MB[kKmax], lo[kKmax], kept_lo[kKmax], kpre[kKmax];
     __shared__ uint32_t kept[kKmax], nkt[kKmax + 1];
@@ -535,7 +538,7 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ w
     const uint32_t k = 1u << sd.kappa;
     global_t<E>* X = elem_gptr<E>(sd.elem_off) + sd.base;
     const TilePieces tp(sd.m, sd.kappa, sd.tiles, t, T.tile_pofs + 2 * g);
-    for (uint32_t b = tid; b < k; b += kTabThreads) {
+    for (uint32_t b = tid; b < k; b += kFixThreads) {
         const uint64_t e = sd.tab_off + t * k + b;
         const uint64_t gb = sd.bk_off + b;
         const Stats st = piece_stats(tp.of(b), T.cnt[e], T.S[gb], T.N[gb]);
@@ -552,7 +555,7 @@ __global__ __launch_bounds__(kTabThreads) void k_scatter(const E* __restrict__ w
     if (wv == 0) wave_exclusive_scan(nkt, k);
     block_sync();
     const uint32_t nfree = nkt[k];
-    for (uint32_t i = tid; i < nfree; i += kTabThreads) {
+    for (uint32_t i = tid; i < nfree; i += kFixThreads) {
         const uint32_t b = upper_index(nkt, k, i);  // piece of the free slot
         const uint64_t j = i - nkt[b];
         uint64_t x;
@@ -646,7 +649,7 @@ hipError_t launch_children(const LevelTables& t, uint32_t tile_limit, LeafDesc* 
 template <typename E>
 static hipError_t gather_t(uint8_t* ws, const LevelTables& t, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_gather<E>, dim3(static_cast<uint32_t>(t.ntiles)), dim3(kTabThreads), 0,
+    hipLaunchKernelGGL(k_gather<E>, dim3(static_cast<uint32_t>(t.ntiles)), dim3(kFixThreads), 0,
                        stream, reinterpret_cast<E*>(ws), t);
     return hipGetLastError();
 }
@@ -654,7 +657,7 @@ static hipError_t gather_t(uint8_t* ws, const LevelTables& t, hipStream_t stream
 template <typename E>
 static hipError_t scatter_t(const uint8_t* ws, const LevelTables& t, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_scatter<E>, dim3(static_cast<uint32_t>(t.ntiles)), dim3(kTabThreads), 0,
+    hipLaunchKernelGGL(k_scatter<E>, dim3(static_cast<uint32_t>(t.ntiles)), dim3(kFixThreads), 0,
                        stream, reinterpret_cast<const E*>(ws), t);
     return hipGetLastError();
 }
