@@ -164,7 +164,6 @@ struct RoughLayout {
     uint32_t counts;   // per-wave counters: kRoughWaves rows of (kmax + 1) u32
     uint32_t slot_tab; // per-wave slot table: kRoughWaves rows of kmax uint2
     uint32_t tables;   // offset of the per-piece tables
-    uint32_t bpiece;   // piece of every label block, one byte each
     uint32_t total;
 };
 
@@ -178,9 +177,7 @@ __host__ __device__ __forceinline__ RoughLayout rough_layout(uint32_t T, uint32_
     if (overlay > L.stage) L.stage = align16(overlay);
     // lo: (kmax+1) u64; qoff, cap, fill, ovt, hot, nblk: (kmax+1) u32 each; 16 u32 misc
     L.tables = L.stage;
-    L.bpiece = L.tables + align16((kmax + 1) * 8u + 6u * (kmax + 1) * 4u + 64u);
-    // a piece of c items touches at most c/16 + 2 label blocks
-    L.total = L.bpiece + align16(T / 16u + 2u * kmax + 16u);
+    L.total = L.tables + align16((kmax + 1) * 8u + 6u * (kmax + 1) * 4u + 64u);
     return L;
 }
 

@@ -179,7 +179,6 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     uint16_t* fs = reinterpret_cast<uint16_t*>(smem);                    // overlays lab
     uint32_t* H = reinterpret_cast<uint32_t*>(smem + L.counts);          // overlays stage
     uint2* WT = reinterpret_cast<uint2*>(smem + L.slot_tab);              // overlays stage
-    uint8_t* bpiece = smem + L.bpiece;
     uint64_t* lo = reinterpret_cast<uint64_t*>(smem + L.tables);
     uint32_t* qoff = reinterpret_cast<uint32_t*>(lo + kmax + 1);
     uint32_t* cap = qoff + kmax + 1;
@@ -233,22 +232,22 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     if (wv == 0) wave_exclusive_scan(nblk, k);
     lds_barrier();
     const uint32_t nblocks = nblk[k];
-    for (uint32_t b = wv; b < k; b += kRoughWaves) {
-        const uint32_t b0 = uniform(nblk[b]), nb = uniform(nblk[b + 1]) - b0;
-        for (uint32_t j = lane; j < nb; j += 64) bpiece[b0 + j] = static_cast<uint8_t>(b);
-    }
-    lds_barrier();
 
     // While the loads are in flight: the Philox blocks of this thread's label
     // blocks (a tile touches at most T/16 + 2k <= 2 * kRoughThreads blocks).
     constexpr int kBlk = 2;
     static_assert((kTileBytesMax / 4) / 16 + 2 * kKmax <= kBlk * kRoughThreads, "label blocks per thread");
+    // The piece of label block i: the last piece whose blocks start at or
+    // before i (pieces without blocks share their start with the next one).
     Word4 lw[kBlk];
+    uint32_t bb[kBlk];
 #pragma unroll
     for (int u = 0; u < kBlk; ++u) {
         const uint32_t i = tid + u * kRoughThreads;
+        bb[u] = 0;
         if (i < nblocks) {
-            const uint32_t b = bpiece[i];
+            const uint32_t b = upper_index(nblk, k, i);
+            bb[u] = b;
             lw[u] = label_block(key, sd.level, ((pbase + lo[b]) >> 4) + (i - nblk[b]));
         }
     }
@@ -268,14 +267,14 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     }
     block_sync();  // staging is free: labels and per-wave counters overlay it
 
-    // Labels in staging order: block i of the tile belongs to piece
-    // bpiece[i]; d is the offset of its first position from the piece start.
+    // Labels in staging order: block i of the tile belongs to piece bb[u];
+    // d is the offset of its first position from the piece start.
     const uint32_t sh = 8 - kappa;
 #pragma unroll
     for (int u = 0; u < kBlk; ++u) {
         const uint32_t i = tid + u * kRoughThreads;
         if (i >= nblocks) continue;
-        const uint32_t b = bpiece[i];
+        const uint32_t b = bb[u];
         const uint64_t p0 = pbase + lo[b];
         const uint64_t B = (p0 >> 4) + (i - nblk[b]);
         const Word4 v = lw[u];
