@@ -213,23 +213,44 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
         }
     }
 
-    // While the loads are in flight: the piece tables and the label blocks
-    // (16 positions per Philox call) each piece touches.  The barriers here
-    // wait for LDS operations only, not for the loads.
-    for (uint32_t b = tid; b < k; b += kRoughThreads) {
-        const Piece pc = tp.of(b);
-        lo[b] = pc.lo;
-        cap[b] = static_cast<uint32_t>(pc.cap);
-        qoff[b] = tp.start(b);
-        uint32_t nb = 0;
-        if (pc.cap) {
-            const uint64_t p0 = pbase + pc.lo, p1 = p0 + pc.cap - 1;
-            nb = static_cast<uint32_t>((p1 >> 4) - (p0 >> 4) + 1);
+    // While the loads are in flight: the piece tables (waves 1..) and, in
+    // wave 0, the label blocks (16 positions per Philox call) each piece
+    // touches, scanned in registers (lane l takes pieces 4l .. 4l + 3).  The
+    // barrier here waits for LDS operations only, not for the loads.
+    static_assert(kKmax <= 4 * 64, "wave 0 takes four pieces per lane");
+    if (wv == 0) {
+        uint32_t nb[4];
+        uint32_t own = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t b = 4 * lane + q;
+            nb[q] = 0;
+            if (b < k) {
+                const Piece pc = tp.of(b);
+                if (pc.cap) {
+                    const uint64_t p0 = pbase + pc.lo, p1 = p0 + pc.cap - 1;
+                    nb[q] = static_cast<uint32_t>((p1 >> 4) - (p0 >> 4) + 1);
+                }
+            }
+            own += nb[q];
         }
-        nblk[b] = nb;
+        const uint32_t incl = wave_inclusive_sum(own);
+        uint32_t run = incl - own;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t b = 4 * lane + q;
+            if (b < k) nblk[b] = run;
+            run += nb[q];
+        }
+        if (lane == 63) nblk[k] = incl;
+    } else {
+        for (uint32_t b = tid - 64; b < k; b += kRoughThreads - 64) {
+            const Piece pc = tp.of(b);
+            lo[b] = pc.lo;
+            cap[b] = static_cast<uint32_t>(pc.cap);
+            qoff[b] = tp.start(b);
+        }
     }
-    lds_barrier();
-    if (wv == 0) wave_exclusive_scan(nblk, k);
     lds_barrier();
     const uint32_t nblocks = nblk[k];
 
