@@ -173,7 +173,12 @@ __host__ __device__ __forceinline__ RoughLayout rough_layout(uint32_t T, uint32_
     L.counts = align16(T);
     L.slot_tab = L.counts + align16(kRoughWaves * (kmax + 1) * 4u);
     const uint32_t overlay = L.slot_tab + kRoughWaves * kmax * 8u;
+    // The staging area spans kTileBytesMax bytes whatever T is: a workgroup's
+    // threads read that many bytes of slots into registers at fixed offsets
+    // (the slots past the tile are read and ignored).  A shorter tile would
+    // not raise occupancy: two 1024-thread workgroups fill a CU already.
     L.stage = align16(T * w);
+    if (L.stage < kTileBytesMax) L.stage = kTileBytesMax;
     if (overlay > L.stage) L.stage = align16(overlay);
     // lo: (kmax+1) u64; qoff, cap, fill, ovt, hot, nblk: (kmax+1) u32 each; 16 u32 misc
     L.tables = L.stage;

@@ -278,14 +278,12 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     // Wave wv owns read-order slots [wv * 64R, (wv + 1) * 64R); round r gives
     // lane l the slot wv * 64R + 64r + l.
     const uint32_t first = wv * 64u * R + lane;
-    // Reads of slots past the tile's end fetch slot 0 (in bounds, unused) so
-    // that the loop has no branches and its reads overlap.
+    // Slots past the tile's end are read too (the staging area spans all
+    // kRoughThreads * R slots) and ignored: one base address, no branches,
+    // every read at a constant offset.
     ElemRegs<E, R> data;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t q = first + 64u * r;
-        data.set(r, stage[q < ts ? q : 0u]);
-    }
+    for (int r = 0; r < R; ++r) data.set(r, stage[first + 64u * r]);
     block_sync();  // staging is free: labels and per-wave counters overlay it
 
     // Labels in staging order: block i of the tile belongs to piece bb[u];
@@ -386,10 +384,14 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     const uint32_t nfree = hot[k];
     const bool use_list = nfree <= prm.tile / 2;
     if (use_list) {
-        for (uint32_t b = tid; b < k; b += kRoughThreads) {
-            const uint32_t base = hot[b], f0 = qoff[b] + fill[b], nh = cap[b] - fill[b];
-            for (uint32_t j = 0; j < nh; ++j) fs[base + j] = static_cast<uint16_t>(f0 + j);
-        }
+        // kRoughThreads / k threads per piece, each writing every
+        // (kRoughThreads / k)-th of its holes
+        static_assert(kRoughThreads == 1024 && kKmax <= 1024, "threads per piece: 2^(10 - kappa)");
+        const uint32_t tsh = 10u - kappa;
+        const uint32_t b = tid >> tsh;
+        const uint32_t base = hot[b], f0 = qoff[b] + fill[b], nh = cap[b] - fill[b];
+        for (uint32_t j = tid & ((1u << tsh) - 1u); j < nh; j += 1u << tsh)
+            fs[base + j] = static_cast<uint16_t>(f0 + j);
     }
     for (uint32_t i = tid; i < kRoughWaves * k; i += kRoughThreads) {
         const uint32_t w = i >> kappa, l = i & (k - 1);
@@ -417,23 +419,18 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
             pk[r] = placed ? (e.x & 0xFFFFu) + rr : f;
         }
     } else {
+        // every round again, without branches: the piece of a staged item
+        // is the last one whose holes start at or before it (kappa halving
+        // steps over the hole offsets, k being a power of two)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const uint32_t q = first + 64u * r;
-            if (q < ts) {
-                const uint32_t l = pk[r] & 0xFFu, rr = pk[r] >> 8;
-                const uint2 e = WT[wv * k + l];
-                const int32_t B = static_cast<int32_t>(e.x) >> 16;
-                uint32_t slot;
-                if (static_cast<int32_t>(rr) < B) {
-                    slot = (e.x & 0xFFFFu) + rr;
-                } else {
-                    const uint32_t s = e.y + rr;
-                    const uint32_t bb = upper_index(hot, k, s);
-                    slot = qoff[bb] + fill[bb] + (s - hot[bb]);
-                }
-                pk[r] = slot;
-            }
+            const uint32_t l = pk[r] & 0xFFu, rr = pk[r] >> 8;
+            const uint2 e = WT[wv * k + (l & (k - 1))];
+            const bool placed = static_cast<int32_t>(rr) < (static_cast<int32_t>(e.x) >> 16);
+            const uint32_t s = e.y + rr;
+            uint32_t bb = 0;
+            for (uint32_t step = k >> 1; step; step >>= 1) bb = hot[bb + step] <= s ? bb + step : bb;
+            pk[r] = placed ? (e.x & 0xFFFFu) + rr : qoff[bb] + fill[bb] + (s - hot[bb]);
         }
     }
     block_sync();  // labels, free list and counters are dead from here on
