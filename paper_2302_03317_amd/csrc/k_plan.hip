@@ -81,7 +81,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_batched(
     SubDesc* __restrict__ subs, LeafDesc* __restrict__ leaves, unsigned long long* __restrict__ counters,
     uint64_t* __restrict__ dsz, uint32_t* __restrict__ err)
 {
-    __shared__ uint64_t wsum[kPlanSums][kPlanWaves];
+    __shared__ uint64_t wsum[kPlanSums + 1][kPlanWaves];
+    __shared__ uint64_t wtot[kPlanSums + 1];
     __shared__ uint32_t bad;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     // the arrays must lie inside the first total_elems elements
@@ -112,7 +113,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_batched(
             v[6] += 1;
         }
     }
-    // exclusive prefix of every sum over the threads
+    // exclusive prefix of every sum over the threads: within each wave, then
+    // over the waves (wave 0 scans the per-wave sums in place; the last row
+    // holds the items of the arrays)
     uint64_t pre[kPlanSums];
 #pragma unroll
     for (int q = 0; q < kPlanSums; ++q) {
@@ -120,26 +123,25 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_batched(
         pre[q] = incl - v[q];
         if (lane == 63) wsum[q][wv] = incl;
     }
-    uint64_t tot_elems = wave_incl64(elems, lane);
-    __shared__ uint64_t welems[kPlanWaves];
-    if (lane == 63) welems[wv] = tot_elems;
-    block_sync();
-    uint64_t total[kPlanSums];
-#pragma unroll
-    for (int q = 0; q < kPlanSums; ++q) {
-        uint64_t run = 0, all = 0;
-        for (uint32_t w = 0; w < kPlanWaves; ++w) {
-            if (w < wv) run += wsum[q][w];
-            all += wsum[q][w];
-        }
-        pre[q] += run;
-        total[q] = all;
+    {
+        const uint64_t incl = wave_incl64(elems, lane);
+        if (lane == 63) wsum[kPlanSums][wv] = incl;
     }
-    uint64_t all_elems = 0;
-    for (uint32_t w = 0; w < kPlanWaves; ++w) all_elems += welems[w];
-    const bool over = total[0] > max_tiles || total[2] > max_chunks || total[4] > max_buckets ||
-                      total[5] > count || all_elems > total_elems;
     block_sync();
+    if (wv == 0) {
+#pragma unroll 1
+        for (int q = 0; q <= kPlanSums; ++q) {
+            const uint64_t x = lane < kPlanWaves ? wsum[q][lane] : 0;
+            const uint64_t incl = wave_incl64(x, lane);
+            if (lane < kPlanWaves) wsum[q][lane] = incl - x;
+            if (lane == kPlanWaves - 1) wtot[q] = incl;
+        }
+    }
+    block_sync();
+#pragma unroll
+    for (int q = 0; q < kPlanSums; ++q) pre[q] += wsum[q][wv];
+    const bool over = wtot[0] > max_tiles || wtot[2] > max_chunks || wtot[4] > max_buckets ||
+                      wtot[5] > count || wtot[kPlanSums] > total_elems;
     if (over || bad) {
         if (tid == 0) {
             *err = 32u;
@@ -183,11 +185,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_batched(
     }
     if (leaf_items) atomicAdd(&counters[2], static_cast<unsigned long long>(leaf_items));
     if (tid == 0) {
-        dsz[0] = total[5];
-        dsz[1] = total[0];
-        dsz[2] = total[2];
-        dsz[3] = total[4];
-        counters[0] = total[6];
+        dsz[0] = wtot[5];
+        dsz[1] = wtot[0];
+        dsz[2] = wtot[2];
+        dsz[3] = wtot[4];
+        counters[0] = wtot[6];
     }
 }
 
