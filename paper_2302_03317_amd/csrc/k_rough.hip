@@ -111,6 +111,13 @@ __device__ __forceinline__ void rank_rounds_atomic(const uint8_t* lab, uint32_t*
     }
 }
 
+// Byte j (0 .. 15) of a 16-byte block held as two 64-bit halves.
+__device__ __forceinline__ uint8_t block_byte(uint64_t lo, uint64_t hi, int32_t j)
+{
+    const uint64_t h = (j & 8) ? hi : lo;
+    return static_cast<uint8_t>(h >> (8 * (j & 7)));
+}
+
 // Checks on the device that LDS atomic adds of one wave instruction that hit
 // the same address return their old values in lane order, for random label
 // patterns (1 to 256 labels, all or some lanes active); out[0] counts lanes
@@ -298,42 +305,40 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
         const uint64_t B = (p0 >> 4) + (i - nblk[b]);
         const Word4 v = lw[u];
         const int32_t d = static_cast<int32_t>(static_cast<uint32_t>(B << 4) - static_cast<uint32_t>(p0));
-        const uint32_t c = cap[b];
+        const int32_t c = static_cast<int32_t>(cap[b]);
         const int32_t q0 = static_cast<int32_t>(qoff[b]) + d;
-        if (d >= 0 && static_cast<uint32_t>(d) + 16u <= c) {
-            // a whole block inside the piece: its 16 label bytes as words
-            // (top kappa bits of every byte), stored as four aligned words,
-            // or as three byte-aligned middle words and four edge bytes
-            const uint32_t msk = 0x01010101u * (0xFFu >> sh);
-            const uint32_t L0 = (v.x >> sh) & msk, L1 = (v.y >> sh) & msk;
-            const uint32_t L2 = (v.z >> sh) & msk, L3 = (v.w >> sh) & msk;
-            const uint32_t a = static_cast<uint32_t>(q0) & 3u;
-            uint8_t* out = lab + q0;
-            if (a == 0) {
-                uint32_t* ow = reinterpret_cast<uint32_t*>(out);
-                ow[0] = L0;
-                ow[1] = L1;
-                ow[2] = L2;
-                ow[3] = L3;
-            } else {
-                uint32_t* ow = reinterpret_cast<uint32_t*>(out - a);  // aligned
-                const uint32_t sft = 4u - a;
-                ow[1] = __builtin_amdgcn_alignbyte(L1, L0, sft);
-                ow[2] = __builtin_amdgcn_alignbyte(L2, L1, sft);
-                ow[3] = __builtin_amdgcn_alignbyte(L3, L2, sft);
-                // bytes 0 .. 3-a of the block end the first word, bytes
-                // 16-a .. 15 begin the fifth
-                for (uint32_t j = 0; j < 4; ++j) {
-                    if (j < sft) out[j] = static_cast<uint8_t>(L0 >> (8 * j));
-                    else out[12 + j] = static_cast<uint8_t>(L3 >> (8 * j));
-                }
-            }
-        } else {
+        // The block's 16 label bytes (top kappa bits of every byte) sit at
+        // staging bytes q0 .. q0 + 15, of which [s0, s1) lie in the piece.
+        // One code path for every block: the aligned words fully inside
+        // [s0, s1) as words, the at most three bytes before the first and
+        // after the last such word one by one (neighbouring blocks and
+        // pieces write the other bytes of those words).
+        const uint32_t msk = 0x01010101u * (0xFFu >> sh);
+        const uint32_t L0 = (v.x >> sh) & msk, L1 = (v.y >> sh) & msk;
+        const uint32_t L2 = (v.z >> sh) & msk, L3 = (v.w >> sh) & msk;
+        const int32_t s0 = q0 + (d < 0 ? -d : 0);
+        const int32_t s1 = q0 + (c - d < 16 ? c - d : 16);
+        const int32_t wb = q0 >> 2;  // the word holding byte q0 (floor)
+        const uint32_t a = static_cast<uint32_t>(q0) & 3u;
+        const int32_t up0 = (s0 + 3) & ~3;  // first word boundary at or after s0
 #pragma unroll
-            for (uint32_t j = 0; j < 16; ++j)
-                if (static_cast<uint32_t>(d + static_cast<int32_t>(j)) < c)
-                    lab[q0 + static_cast<int32_t>(j)] =
-                        static_cast<uint8_t>(__builtin_amdgcn_ubfe(word_of(v, j >> 2), 8 * (j & 3) + sh, kappa));
+        for (int m = 0; m < 5; ++m) {
+            const uint32_t lo_w = m == 1 ? L0 : m == 2 ? L1 : m == 3 ? L2 : m == 4 ? L3 : 0u;
+            const uint32_t hi_w = m == 0 ? L0 : m == 1 ? L1 : m == 2 ? L2 : m == 3 ? L3 : 0u;
+            const uint32_t W = a ? __builtin_amdgcn_alignbyte(hi_w, lo_w, 4u - a) : hi_w;
+            const int32_t p = 4 * (wb + m);
+            if (p >= s0 && p + 4 <= s1) reinterpret_cast<uint32_t*>(lab)[wb + m] = W;
+        }
+        const int32_t lead_end = up0 < s1 ? up0 : s1;
+        const int32_t tail_beg = (s1 & ~3) > up0 ? (s1 & ~3) : up0;
+        const uint64_t Llo = (static_cast<uint64_t>(L1) << 32) | L0;
+        const uint64_t Lhi = (static_cast<uint64_t>(L3) << 32) | L2;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const int32_t p = s0 + e;
+            if (p < lead_end) lab[p] = block_byte(Llo, Lhi, p - q0);
+            const int32_t p2 = tail_beg + e;
+            if (p2 < s1) lab[p2] = block_byte(Llo, Lhi, p2 - q0);
         }
     }
     for (uint32_t i = tid; i < kRoughWaves * hs; i += kRoughThreads) H[i] = 0;
