@@ -50,9 +50,9 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {
     ("u32_2e32", "rough"): {
         "read_bytes": 17.198e9,
-        "write_bytes": 17.339e9,
+        "write_bytes": 17.338e9,
         "sources": ["k_rough.hip", "common.hpp", "rng.hpp", "kernels.hpp"],
-        "sha256": "0f8a708bf35aec530395194c08a50417ad29b16be87b853797ca4dd7d5a37049",
+        "sha256": "f1019d5a935ac22c0999e29d3891eca8ee89d34823cac771be2f377ed6dfcb3e",
     },
 }
 
