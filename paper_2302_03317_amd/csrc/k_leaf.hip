@@ -203,7 +203,7 @@ __device__ __forceinline__ void split_wave(uint16_t* idx, const uint8_t* lab, ui
 
 // One leaf of a size class: at most kThreads * ROUNDS items, LDS laid out
 // for the class capacity `cap` at smem.  Called by the whole workgroup.
-template <typename E, int ROUNDS>
+template <typename E, int ROUNDS, bool ATOMIC>
 __device__ __forceinline__ void leaf_body(const LeafDesc ld, const Params& prm, uint32_t cap, uint8_t* smem)
 {
     constexpr int EMAX = ROUNDS;
@@ -322,7 +322,7 @@ __device__ __forceinline__ void leaf_body(const LeafDesc ld, const Params& prm, 
             const uint32_t e = uniform(cur[i]);
             const uint32_t s0 = seg_start(e), len = seg_len(e);
             uint32_t* out = nxt + tmpk[i];
-            if (prm.rank_atomic) {
+            if constexpr (ATOMIC) {
                 switch (kappa_in_tile(len, prm)) {
                 case 1: split_workgroup<1, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
                 case 2: split_workgroup<2, ROUNDS, true>(idx, lab, H, hs, out, s0, len, tid, wv, lane, first); break;
@@ -354,7 +354,7 @@ __device__ __forceinline__ void leaf_body(const LeafDesc ld, const Params& prm, 
             const uint32_t s0 = seg_start(e), len = seg_len(e);
             uint32_t* Hw = H + wv * hs;
             uint32_t* out = nxt + tmpk[i];
-            if (prm.rank_atomic) {
+            if constexpr (ATOMIC) {
                 switch (kappa_in_tile(len, prm)) {
                 case 1: split_wave<1, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane, first); break;
                 case 2: split_wave<2, ROUNDS, true>(idx, lab, Hw, out, s0, len, lane, first); break;
@@ -415,7 +415,7 @@ __device__ __forceinline__ void leaf_body(const LeafDesc ld, const Params& prm, 
 // One size class of leaves, MINW waves per SIMD, in persistent workgroups:
 // each takes the next leaf of the class from the work counter *qctr until
 // *count leaves are taken.
-template <typename E, int ROUNDS, int MINW>
+template <typename E, int ROUNDS, int MINW, bool ATOMIC>
 __global__ __launch_bounds__(kThreads, MINW) void k_leaf_persistent(const LeafDesc* __restrict__ leaves,
                                                                     const unsigned long long* __restrict__ count,
                                                                     unsigned long long* __restrict__ qctr,
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kThreads, MINW) void k_leaf_persistent(const LeafDe
         const unsigned long long i = take[it & 1u];
         if (i >= total) break;
         if (threadIdx.x == 0) take[(it + 1) & 1u] = atomicAdd(qctr, 1ull);
-        leaf_body<E, ROUNDS>(leaves[i], prm, cap, smem);
+        leaf_body<E, ROUNDS, ATOMIC>(leaves[i], prm, cap, smem);
         block_sync();  // the next leaf reuses the LDS
     }
 }
@@ -482,13 +482,15 @@ hipError_t leaf_class_persistent_t(const LeafDesc* leaves, const unsigned long l
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // one kernel per rank method (the other method's split code would only
+    // add registers)
+    auto* kern = prm.rank_atomic ? &k_leaf_persistent<E, ROUNDS, MINW, true> : &k_leaf_persistent<E, ROUNDS, MINW, false>;
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&k_leaf_persistent<E, ROUNDS, MINW>), kThreads, LL.total);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), kThreads,
+                                                         LL.total);
     if (e != hipSuccess) return e;
     const uint32_t grid = static_cast<uint32_t>(std::max(1, cus) * std::max(1, per_cu));
-    hipLaunchKernelGGL((k_leaf_persistent<E, ROUNDS, MINW>), dim3(grid), dim3(kThreads), LL.total, stream,
-                       leaves, count, qctr, prm, cap);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), LL.total, stream, leaves, count, qctr, prm, cap);
     return hipGetLastError();
 }
 
@@ -604,19 +606,26 @@ hipError_t launch_leaf_persistent(uint32_t w, const LeafDesc* leaves, const unsi
     }
 }
 
-template <typename E>
-static hipError_t leaf_limits_t()
+template <typename E, bool ATOMIC>
+static hipError_t leaf_limits_method_t()
 {
     using LC = LeafClasses<E>;
     hipError_t e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsS, 8>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsS, 8, ATOMIC>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax - 64);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsM, 6>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsM, 6, ATOMIC>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax - 64);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsL, 4>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_persistent<E, LC::kRoundsL, 4, ATOMIC>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax - 64);
+}
+
+template <typename E>
+static hipError_t leaf_limits_t()
+{
+    const hipError_t e = leaf_limits_method_t<E, true>();
+    return e != hipSuccess ? e : leaf_limits_method_t<E, false>();
 }
 
 hipError_t set_leaf_lds_limits()
