@@ -26,6 +26,11 @@ struct Params {
     // device to serve one wave's same-address LDS atomics in lane order
     // (checked once per device); 0 = one ballot per label bit.
     uint32_t rank_atomic;
+    // 1 = the tile kernel finds the slot of every staged item by a search
+    // over the pieces' free slots, as it does when they do not fit its list;
+    // 0 = by the list whenever it fits (both give the same slots; 1 exists
+    // so that tests can run the search).
+    uint32_t slot_search;
 };
 
 // Device memory seen through the global address space: its loads and stores

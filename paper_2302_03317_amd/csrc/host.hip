@@ -208,6 +208,7 @@ struct Context {
     LeafLists lists;  // used by blocking calls (under mu)
     bool init = false;
     bool rank_atomic = false;  // see Params::rank_atomic
+    bool slot_search = false;  // see Params::slot_search (IPSCSHUF_SLOTS=search)
     DevBuf subs, tile_sub, tile_pofs, chunk_sub, bk_sub, cnt, mpre, kpre, chA, chB, N, S, M, K, MB, wsp, total, ws,
         leaves, leaves_cls, big, gfy, err, counters, probe;
     HostSet host;
@@ -498,10 +499,13 @@ int engine_step(Context& C, Engine& E, hipStream_t stream, shuf_stats_t& st)
         HIP_TRY(probe_lds_lane_order(stream, static_cast<unsigned long long*>(pbuf), &lane_ordered));
         const char* rank_env = std::getenv("IPSCSHUF_RANK");
         C.rank_atomic = lane_ordered && !(rank_env && std::strcmp(rank_env, "ballot") == 0);
+        const char* slot_env = std::getenv("IPSCSHUF_SLOTS");
+        C.slot_search = slot_env && std::strcmp(slot_env, "search") == 0;
         C.init = true;
         std::call_once(g_exit_hook, [] { std::atexit(release_all); });
     }
     prm.rank_atomic = C.rank_atomic ? 1u : 0u;
+    prm.slot_search = C.slot_search ? 1u : 0u;
     const uint32_t kmax = 1u << prm.kmax_log2;
     const uint64_t tile_limit = prm.tile - kmax;  // subproblems up to this size finish in LDS
     const bool dry = E.dry;
@@ -786,7 +790,7 @@ Engine make_engine(uint32_t w, const shuf_params_t& p)
 {
     Engine E;
     E.w = w;
-    E.prm = Params{p.tile, p.kmax_log2, p.n0, p.lmax};
+    E.prm = Params{p.tile, p.kmax_log2, p.n0, p.lmax, 0, 0};
     return E;
 }
 
@@ -1027,7 +1031,7 @@ int shuffle_batched_async_workspace_bytes(uint64_t count, uint64_t total_elems, 
     const int rc = batched_params(params, elem_bytes, &p);
     if (rc != SHUF_OK) return rc;
     if (count == 0 || count > kAsyncMaxCount || total_elems >= kMaxElements) return SHUF_EUNSUPPORTED;
-    *out_bytes = async_layout(count, total_elems, elem_bytes, Params{p.tile, p.kmax_log2, p.n0, p.lmax, 0}).total;
+    *out_bytes = async_layout(count, total_elems, elem_bytes, Params{p.tile, p.kmax_log2, p.n0, p.lmax, 0, 0}).total;
     return SHUF_OK;
 }
 
@@ -1053,7 +1057,7 @@ int shuffle_batched_async(void* ptr, const uint64_t* offsets, uint64_t count, ui
     int rc = batched_params(params, elem_bytes, &sp);
     if (rc != SHUF_OK) return rc;
     if (count == 0 || count > kAsyncMaxCount || total_elems >= kMaxElements) return SHUF_EUNSUPPORTED;
-    Params prm{sp.tile, sp.kmax_log2, sp.n0, sp.lmax, 0};
+    Params prm{sp.tile, sp.kmax_log2, sp.n0, sp.lmax, 0, 0};
     const AsyncLayout L = async_layout(count, total_elems, elem_bytes, prm);
     if (workspace_bytes < L.total) return SHUF_ENOMEM;
     Context* C = current_context();
@@ -1070,10 +1074,13 @@ int shuffle_batched_async(void* ptr, const uint64_t* offsets, uint64_t count, ui
         HIP_TRY(probe_lds_lane_order(st, static_cast<unsigned long long*>(C->probe.p), &lane_ordered));
         const char* rank_env = std::getenv("IPSCSHUF_RANK");
         C->rank_atomic = lane_ordered && !(rank_env && std::strcmp(rank_env, "ballot") == 0);
+        const char* slot_env = std::getenv("IPSCSHUF_SLOTS");
+        C->slot_search = slot_env && std::strcmp(slot_env, "search") == 0;
         C->init = true;
         std::call_once(g_exit_hook, [] { std::atexit(release_all); });
     }
     prm.rank_atomic = C->rank_atomic ? 1u : 0u;
+    prm.slot_search = C->slot_search ? 1u : 0u;
     uint8_t* W = static_cast<uint8_t*>(workspace);
     uint32_t* err = reinterpret_cast<uint32_t*>(W + L.header);
     unsigned long long* counters = reinterpret_cast<unsigned long long*>(W + L.header + 8);  // 6 words

@@ -387,7 +387,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     // of the tile (A = piece start + earlier waves' count, B = capacity left
     // to the wave, C = staged items of smaller labels - B).
     const uint32_t nfree = hot[k];
-    const bool use_list = nfree <= prm.tile / 2;
+    const bool use_list = !prm.slot_search && nfree <= prm.tile / 2;
     if (use_list) {
         // kRoughThreads / k threads per piece, each writing every
         // (kRoughThreads / k)-th of its holes

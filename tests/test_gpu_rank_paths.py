@@ -51,6 +51,19 @@ def test_ballot_ranks_match_oracle_in_own_process():
     assert out.returncode == 0, out.stdout + out.stderr[-2000:]
 
 
+def test_slot_search_matches_oracle_in_own_process():
+    """The tile kernel's slot search (taken when a tile's free slots do not
+    fit its list) forced for every tile, against the oracle."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    env = dict(os.environ, IPSCSHUF_SLOTS="search")
+    print("[gpu] running tests/gpu_slot_search_check.py with IPSCSHUF_SLOTS=search", flush=True)
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "tests", "gpu_slot_search_check.py")],
+                         env=env, capture_output=True, text=True, timeout=240)
+    print(out.stdout, out.stderr[-2000:], flush=True)
+    assert out.returncode == 0, out.stdout + out.stderr[-2000:]
+
+
 def test_many_small_random_cases_match_oracle():
     """120 small random cases (sizes, widths, parameters, seeds) that the
     library accepts, against the oracle: the ranks of every in-tile and tiled
