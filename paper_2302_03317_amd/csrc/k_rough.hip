@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_lane_order_probe(uint32_t trials,
     if (bad) atomicAdd(&out[0], bad);
 }
 
-template <typename E, int R>
+template <typename E, int R, bool ATOMIC>
 __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __restrict__ subs,
                                                     const uint32_t* __restrict__ tile_sub,
                                                     const uint64_t* __restrict__ tile_pofs,
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
 
     uint32_t pk[R];
     uint32_t* Hw = H + wv * hs;
-    if (prm.rank_atomic) {
+    if constexpr (ATOMIC) {
         rank_rounds_atomic<R>(lab, Hw, first, ts, pk);
     } else {
         switch (kappa) {
@@ -467,8 +467,11 @@ hipError_t launch_rough_t(const SubDesc* subs, const uint32_t* tile_sub, const u
     constexpr int R = static_cast<int>(kTileBytesMax / (sizeof(E) * kRoughThreads));
     const RoughLayout L = rough_layout(prm.tile, sizeof(E), 1u << prm.kmax_log2);
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_rough<E, R>), dim3(static_cast<uint32_t>(ntiles)), dim3(kRoughThreads),
-                       L.total, stream, subs, tile_sub, tile_pofs, cnt_tab, prm, dsz);
+    // one kernel per rank method (the other method's code would only add
+    // registers)
+    auto* kern = prm.rank_atomic ? &k_rough<E, R, true> : &k_rough<E, R, false>;
+    hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(ntiles)), dim3(kRoughThreads), L.total, stream, subs,
+                       tile_sub, tile_pofs, cnt_tab, prm, dsz);
     return hipGetLastError();
 }
 
@@ -502,20 +505,23 @@ hipError_t probe_lds_lane_order(hipStream_t stream, unsigned long long* d, bool*
     return hipSuccess;
 }
 
+template <typename E, bool ATOMIC>
+static hipError_t rough_limit_t()
+{
+    constexpr int R = static_cast<int>(kTileBytesMax / (sizeof(E) * kRoughThreads));
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<E, R, ATOMIC>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+}
+
 hipError_t set_rough_lds_limits()
 {
-    constexpr int R4 = static_cast<int>(kTileBytesMax / (4 * kRoughThreads));
-    constexpr int R8 = static_cast<int>(kTileBytesMax / (8 * kRoughThreads));
-    constexpr int R16 = static_cast<int>(kTileBytesMax / (16 * kRoughThreads));
-    hipError_t e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<uint32_t, R4>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<uint64_t, R8>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rough<Elem16, R16>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytesMax);
+    hipError_t e = rough_limit_t<uint32_t, true>();
+    if (e == hipSuccess) e = rough_limit_t<uint32_t, false>();
+    if (e == hipSuccess) e = rough_limit_t<uint64_t, true>();
+    if (e == hipSuccess) e = rough_limit_t<uint64_t, false>();
+    if (e == hipSuccess) e = rough_limit_t<Elem16, true>();
+    if (e == hipSuccess) e = rough_limit_t<Elem16, false>();
+    return e;
 }
 
 }  // namespace ipss
