@@ -339,16 +339,25 @@ __global__ __launch_bounds__(kTabThreads) void k_ws_chunk_sums(LevelTables T)
     if (threadIdx.x == 0) T.wsp[blockIdx.x] = part[0];
 }
 
-__global__ void k_ws_scan_sums(LevelTables T, uint32_t nparts)
+// One wave: the partial sums 64 at a time (one load per lane, a wave scan),
+// rather than one dependent load after the other.
+__global__ __launch_bounds__(64) void k_ws_scan_sums(LevelTables T, uint32_t nparts)
 {
-    if (threadIdx.x != 0) return;
+    const uint32_t lane = threadIdx.x;
     uint64_t run = 0;
-    for (uint32_t i = 0; i < nparts; ++i) {
-        const uint64_t v = T.wsp[i];
-        T.wsp[i] = run;
-        run += v;
+    for (uint32_t i0 = 0; i0 < nparts; i0 += 64) {
+        const uint32_t i = i0 + lane;
+        const uint64_t v = i < nparts ? T.wsp[i] : 0;
+        uint64_t incl = v;
+#pragma unroll
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t u = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += u;
+        }
+        if (i < nparts) T.wsp[i] = run + (incl - v);
+        run += __shfl(incl, 63, 64);
     }
-    *T.total = run;
+    if (lane == 0) *T.total = run;
 }
 
 __global__ __launch_bounds__(kTabThreads) void k_ws_chunk_scan(LevelTables T)
