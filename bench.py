@@ -15,6 +15,8 @@ loop of per-array shuffle_inplace_ex calls on the same data (same bytes out).
 u64 requests (sizes log-uniform in [2^10, 2^26]) admitted under a 64 GiB HBM
 budget into a continuous-batching session, against serving the same stream
 one request at a time; p50/p99 latency and Gelem/s per arrival rate.
+--config batched_u32 times the enqueue-only batched call alone on the
+10,000-array workload (one call per step), for profiling it.
 
 Per-kernel times come from HIP events that the library records on the
 launch stream around every kernel group inside the timed region.  The CPU
@@ -219,6 +221,46 @@ def cpu_baselines(log2n: int, w: int, pip_log2n: int) -> dict:
     return out
 
 
+def batched_async_line(torch, shuf, steps: int, warmup: int, count: int = 10000, seed: int = 2026) -> dict:
+    """The enqueue-only batched call alone on the batched workload (for
+    profiling it): `warmup` untimed calls, then `steps` timed ones."""
+    import numpy as np
+
+    import workloads
+
+    from paper_2302_03317_amd import autotune
+
+    sizes = workloads.log_uniform_sizes(count, 4, 20, seed=seed)
+    offs = workloads.csr_offsets(sizes)
+    host = workloads.batched_identity(sizes)
+    total = int(host.size)
+    found = autotune.lookup(autotune.load_table(), "batched_10000_u32", 4) if count == 10000 else None
+    p, table_version = found if found else (shuf.default_params(0, 4), None)
+    a = torch.from_numpy(host.view(np.int32)).to("cuda:0")
+    ws = torch.zeros(shuf.batched_async_workspace_bytes(count, total, 4, p), dtype=torch.uint8, device="cuda:0")
+    o = torch.tensor(np.asarray(offs, dtype=np.int64), device="cuda:0")
+    seeds = [int.from_bytes(os.urandom(8), "little") for _ in range(warmup + steps)]
+    for s_ in seeds[:warmup]:
+        shuf.shuffle_batched_async(a, o, s_, ws, total, params=p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in seeds[warmup:]:
+        shuf.shuffle_batched_async(a, o, s_, ws, total, params=p)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    err = int(ws[:4].view(torch.int32).item())
+    return {
+        "metric": "batched enqueue-only shuffle throughput", "value": total / (ms / 1e3) / 1e9,
+        "unit": "Gelem/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{count} u32 arrays, sizes floor(2^(4+16U)), {total} elements, identity per "
+                               f"array, sizes seed {seed}; one shuffle_batched_async call per step",
+                   "params": {"tile": p.tile, "kmax_log2": p.kmax_log2, "n0": p.n0, "lmax": p.lmax},
+                   "params_table_version": table_version},
+        "device_error_word": err,
+    }
+
+
 def batched_compare(torch, shuf, count: int = 10000, seed: int = 2026) -> dict:
     """shuffle_batched on `count` ragged u32 arrays vs per-array launches."""
     import numpy as np
@@ -418,7 +460,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="u32_2e32", choices=sorted(CONFIGS) + ["serve_u64"])
+    ap.add_argument("--config", default="u32_2e32", choices=sorted(CONFIGS) + ["serve_u64", "batched_u32"])
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="before the timed region, copy the array once device-to-device (a plain "
@@ -457,6 +499,10 @@ def main() -> int:
                        "rates_per_s": rates, "requests_per_rate": args.serve_requests},
             "sweep": res,
         }), flush=True)
+        return 0
+
+    if args.config == "batched_u32":
+        print(json.dumps(batched_async_line(torch, shuf, args.steps, args.warmup)), flush=True)
         return 0
 
     log2n, w, desc = CONFIGS[args.config]
