@@ -140,12 +140,20 @@ struct TilePieces {
         off[0][1] = last ? len0 : pofs_g[2];
         off[1][1] = last ? len0 + 1 : pofs_g[3];
     }
-    __host__ __device__ __forceinline__ Piece of(uint32_t b) const
+    // Start of region b, floor(b*m/k).
+    __host__ __device__ __forceinline__ uint64_t region_start(uint32_t b) const
     {
-        const uint64_t e0 = (static_cast<uint64_t>(b) * m) >> kappa;
-        const uint64_t e1 = (static_cast<uint64_t>(b + 1) * m) >> kappa;
+        return (static_cast<uint64_t>(b) * m) >> kappa;
+    }
+    // The piece of the region [e0, e1).
+    __host__ __device__ __forceinline__ Piece of_region(uint64_t e0, uint64_t e1) const
+    {
         const uint32_t s = (e1 - e0) != len0 ? 1u : 0u;
         return {e0 + off[s][0], off[s][1] - off[s][0]};
+    }
+    __host__ __device__ __forceinline__ Piece of(uint32_t b) const
+    {
+        return of_region(region_start(b), region_start(b + 1));
     }
     // Items of the tile's pieces 0 .. b-1 (b <= k): the regions before b are
     // b*len0 + n1 items long, n1 of them one longer, so the sum is

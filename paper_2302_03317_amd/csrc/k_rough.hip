@@ -199,24 +199,34 @@ __global__ __launch_bounds__(kRoughThreads, 8) void k_rough(const SubDesc* __res
     const Key key = make_key(sd.seed, sd.stream_id);
 
     // Pieces -> staging, one contiguous run each, straight into LDS.  A
-    // piece's staging offset has a closed form (TilePieces::start), so every
-    // wave sends its pieces' loads before any table is built.
+    // piece's bounds and staging offset have closed forms (TilePieces), so
+    // every wave sends its pieces' loads before any table is built.  Wave wv
+    // takes the consecutive pieces [wv k / 16, (wv + 1) k / 16): a piece's
+    // region end and staging end are the next one's starts, so the closed
+    // forms (64-bit products on the scalar unit) are evaluated once per piece.
     const TilePieces tp(sd.m, kappa, sd.tiles, t, tile_pofs + 2 * g);
     const uint32_t ts = tp.start(k);  // items of the tile
     {
+        static_assert(kRoughWaves == 16, "pieces per wave: k / 16");
         const global_t<uint32_t>* src = reinterpret_cast<const global_t<uint32_t>*>(X);
         uint32_t* dst = reinterpret_cast<uint32_t*>(stage);
-        for (uint32_t b = wv; b < k; b += kRoughWaves) {
-            const Piece pc = tp.of(b);
+        const uint32_t b0 = (wv * k) >> 4, b1 = ((wv + 1) * k) >> 4;
+        uint64_t e0 = tp.region_start(b0);
+        uint32_t st = tp.start(b0);
+        for (uint32_t b = b0; b < b1; ++b) {
+            const uint64_t e1 = tp.region_start(b + 1);
+            const Piece pc = tp.of_region(e0, e1);
             const uint32_t nw = static_cast<uint32_t>(pc.cap) * kWordsPerElem;
             const uint64_t s0 = pc.lo * kWordsPerElem;
-            const uint32_t d0 = tp.start(b) * kWordsPerElem;
+            const uint32_t d0 = st * kWordsPerElem;
             // 4-byte loads: for these short runs they measured faster than
             // the 16-byte form the leaves use
             for (uint32_t j = 0; j < nw; j += 64) {
                 if (j + lane < nw)
                     __builtin_amdgcn_global_load_lds(src + s0 + j + lane, dst + d0 + j, 4, 0, 0);
             }
+            st += static_cast<uint32_t>(pc.cap);
+            e0 = e1;
         }
     }
 
