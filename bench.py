@@ -52,9 +52,9 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {
     ("u32_2e32", "rough"): {
         "read_bytes": 17.198e9,
-        "write_bytes": 17.335e9,
+        "write_bytes": 17.342e9,
         "sources": ["k_rough.hip", "common.hpp", "rng.hpp", "kernels.hpp"],
-        "sha256": "2ef89f8253d9876b375fcdae25ca0ceb48fe5cc2256f5a6edd4e36e24b05ae93",
+        "sha256": "c5e248c53023ab972b21fab3b64e3797d48a957ebc625263ee911ade9c4c43db",
     },
 }
 
