@@ -4,7 +4,8 @@
 // floor((b+1)*m/k)), piece t starts at floor(t*len/P)), and the closed-form
 // staging offsets equal the running sums of the piece sizes, for random
 // subproblem sizes, bucket counts and tile counts, including sizes beyond
-// 2^32.  Built with hipcc --cuda-host-only.
+// 2^32; and the tile kernel's split of the pieces among its 16 waves covers
+// every piece once.  Built with hipcc --cuda-host-only.
 #include <cstdio>
 #include <random>
 
@@ -57,6 +58,24 @@ int main()
                 }
                 ++checked;
             }
+        }
+    }
+    // The tile kernel's loads: wave w (of 16) takes the consecutive pieces
+    // [w k / 16, (w + 1) k / 16); for every k these ranges cover [0, k) once.
+    for (uint32_t kap = 0; kap <= 8; ++kap) {
+        const uint32_t k = 1u << kap;
+        uint32_t next = 0;
+        for (uint32_t w = 0; w < 16; ++w) {
+            const uint32_t b0 = (w * k) >> 4, b1 = ((w + 1) * k) >> 4;
+            if (b0 != next || b1 < b0) {
+                std::printf("wave ranges k=%u w=%u: [%u, %u) after %u\n", k, w, b0, b1, next);
+                return 1;
+            }
+            next = b1;
+        }
+        if (next != k) {
+            std::printf("wave ranges k=%u end at %u\n", k, next);
+            return 1;
         }
     }
     std::printf("ok %ld\n", checked);
